@@ -1,0 +1,195 @@
+/*
+ * cavity.h -- C ABI of the MI355X cavity library (libcavity.so).
+ *
+ * One GPU's share of an explicit pseudo-time solver for the 3D buoyancy-driven
+ * cavity (Xue & Roy, "Multi-GPU Performance Optimization of a CFD Code using
+ * OpenACC on Different Platforms", arXiv:2006.02602):
+ *   - the residual + first-order Euler update sweep of the artificial-
+ *     compressibility Boussinesq equations (Sec. 2, Eq. 1-3; Sec. 3.1),
+ *     with the wall boundary conditions and the per-iteration pressure
+ *     rescale at the cavity centre (Sec. 2),
+ *   - in-device packing / unpacking of noncontiguous halo faces into one
+ *     contiguous buffer with a ghost width per variable (Sec. 4.5,
+ *     "Optimized V1/V2/V3", Listings 1-2).
+ *
+ * Conventions shared by every call
+ *   - State layout.  q is ONE allocation of 5 fields in the order
+ *     p, u, v, w, T (Listing 2: var 1 is pressure, vars 2..5 the velocities
+ *     and temperature).  Field f, cell (i, j, k) lives at
+ *         q[((f*(nk+2g) + (k+g))*(nj+2g) + (j+g))*(ni+2g) + (i+g)]
+ *     with g = ng = 2 ghost layers per side (Listing 1: "interior cell index
+ *     starts at 3"), i fastest and k slowest (Sec. 3.1), (i,j,k) = (x,y,z).
+ *     Interior cells are 0 <= i < ni etc.  Edge and corner ghost cells are
+ *     never read or written.  Element type: double when dtype == CAV_F64.
+ *   - Pointers are DEVICE pointers unless the comment says (host).  The
+ *     caller owns every buffer; the library allocates no device memory and
+ *     keeps no pointer after a call returns.
+ *   - Every call enqueues its work on `stream` (0 = the null stream) and
+ *     returns without waiting, except cavity_residual_norm, which waits.
+ *   - Arguments are validated on the host BEFORE anything is enqueued; on
+ *     any error nothing is enqueued and a negative CAV_E* code is returned.
+ *     cavity_last_error() then describes the failure (thread-local text).
+ *   - The library keeps no per-problem state: calls are reentrant, but two
+ *     calls that write the same buffers must be ordered by the caller.
+ */
+#ifndef CAVITY_H_
+#define CAVITY_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------ */
+#define CAV_OK          0
+#define CAV_EINVAL    (-1)  /* bad argument: null pointer, sizes, split, widths */
+#define CAV_ESIZE     (-2)  /* a caller buffer is smaller than required        */
+#define CAV_EHIP      (-3)  /* a HIP launch or runtime call failed             */
+#define CAV_ENONFINITE (-4) /* a residual norm is NaN or infinite              */
+#define CAV_ENOSYS    (-5)  /* operation not available in this build           */
+
+/* ---- element types ---------------------------------------------------- */
+#define CAV_F64 0
+
+/* Grid of one cavity (or one GPU's block of it).  ni, nj, nk >= 2 interior
+ * cells; ng must be 2 (the pressure stencil reaches two cells, Sec. 3.1). */
+typedef struct {
+    int32_t ni, nj, nk;
+    int32_t ng;
+    int32_t dtype;          /* CAV_F64 */
+} cav_grid;
+
+/* Physical and numerical parameters (Sec. 2).  Nondimensional, free-fall
+ * scaling on the unit cube: nu = sqrt(Pr/Ra), alpha = 1/sqrt(Ra*Pr),
+ * buoyancy +(T - t_inf) along +z.  The hot wall is x = 0, the cold wall
+ * x = 1, the other four walls adiabatic.
+ *   cfl    pseudo-time CFL number of the local time step
+ *   eps4   coefficient of the fourth-difference pressure dissipation (Eq. 1)
+ *   kappa, u_ref   artificial compressibility: beta^2 = max(|V|^2, kappa*u_ref^2)
+ *   t_hot_field    must be NULL in this build. */
+typedef struct {
+    double Ra, Pr, cfl, eps4, kappa, u_ref, t_hot, t_cold, t_inf;
+    const void* t_hot_field;
+} cav_params;
+
+/* Virtual domain decomposition for the halo exchange (Sec. 3.2; Sec. 4.5).
+ * split = (Pi, Pj, Pk) subdomains along i, j, k; each must divide the grid
+ * extent.  width[f] = ghost layers exchanged for field f (order p,u,v,w,T),
+ * 0 <= width[f] <= ng and width[f] <= every subdomain extent.  The paper's
+ * stencil-based widths (Optimized V2) are {2,1,1,1,1}. */
+typedef struct {
+    int32_t split[3];
+    int32_t width[5];
+} cav_halo;
+
+/* Number of elements of one state array (all 5 fields, ghosts included):
+ * 5*(ni+2ng)*(nj+2ng)*(nk+2ng).  Returns 0 for an invalid grid. */
+size_t cavity_state_elems(const cav_grid* grid);
+
+/* Bytes of the workspace `ws` that cavity_step and cavity_residual_norm
+ * need (per-block residual partials and the final norms).  0 if invalid. */
+size_t cavity_workspace_bytes(const cav_grid* grid);
+
+/* Bytes of the contiguous halo buffer for `halo` on `grid` (Sec. 4.5):
+ * sum over subdomains s = a + Pi*(b + Pj*c), over the cut faces of s in
+ * the order -x,+x,-y,+y,-z,+z (faces on a cavity wall are skipped), over
+ * the fields p,u,v,w,T with width > 0, of width * (face area of s) *
+ * sizeof(element).  Within a segment, elements run over the sender's box
+ * of `width` layers next to the face in (k, j, i) order, i fastest
+ * (Listing 1's index order).  Returns 0 for invalid arguments. */
+size_t halo_buffer_bytes(const cav_grid* grid, const cav_halo* halo);
+
+/* Seeded initial state (not part of the timed path).  Interior:
+ *   u, v, w = noise(seed, 1..3, idx), p = 0,
+ *   T = t_hot + (t_cold - t_hot) * (i + 1/2)/ni + noise(seed, 4, idx),
+ * where idx = i + ni*(j + nj*k) and noise(seed, f, idx) = (2r - 1)*noise_amp
+ * with r = (z >> 11) * 2^-53, z the output number f*2^40 + idx (0-based) of
+ * the SplitMix64 generator seeded with `seed` (Steele, Lea & Flood, 2014).
+ * Then the wall ghost layers are filled as cavity_step does.
+ * q: device, cavity_state_elems(grid) elements, written. */
+int cavity_init(const cav_grid* grid, const cav_params* prm, uint64_t seed,
+                double noise_amp, void* q, hipStream_t stream);
+
+/* Advance the state `nsteps` >= 0 pseudo-time steps (Sec. 2; Sec. 3.1).
+ * Each step, in this order:
+ *   1. fill the wall ghost layers of q (Sec. 2: no-slip velocity; T fixed
+ *      on the hot/cold walls and zero-gradient on the adiabatic walls,
+ *      second order; p extrapolated linearly, one-sided second order),
+ *   2. if halo != NULL: halo_pack into halo_buf, then halo_unpack from it
+ *      (all virtual subdomains live in q, so the exchange is a round trip),
+ *   3. for every interior cell: residuals R_p, R_u, R_v, R_w, R_T of
+ *      Eq. 1-3 (second-order central differences; fourth-difference
+ *      pressure dissipation), local time step, q' = q + dt*R written to
+ *      q_tmp (Jacobi: every residual uses the old state),
+ *   4. p' -= p'(ni/2, nj/2, nk/2) over the interior (Sec. 2, rescale at the
+ *      centre point every iteration),
+ *   5. swap q and q_tmp.
+ * On return the newest state is in q (for odd nsteps the library copies it
+ * back from q_tmp); q_tmp holds scratch.  The residual L2 norms of the last
+ * step are left in ws for cavity_residual_norm.
+ * q, q_tmp: device, cavity_state_elems(grid) elements each, distinct.
+ * ws: device, >= cavity_workspace_bytes(grid) = ws_bytes.
+ * halo_buf: device, >= halo_buffer_bytes(grid, halo) = halo_bytes; ignored
+ * (may be NULL) when halo == NULL. */
+int cavity_step(const cav_grid* grid, const cav_params* prm, const cav_halo* halo,
+                void* q, void* q_tmp, void* ws, size_t ws_bytes,
+                void* halo_buf, size_t halo_bytes, int32_t nsteps,
+                hipStream_t stream);
+
+/* Gather every halo segment of `halo` (layout: halo_buffer_bytes) from q
+ * into the contiguous buffer buf (Sec. 4.5, Listings 1-2: the parallel
+ * in-device pack of the "Optimized" versions; V3 covers i, j and k faces).
+ * One kernel launch.  q: device, read.  buf: device, buf_bytes >=
+ * halo_buffer_bytes(grid, halo), written. */
+int halo_pack(const cav_grid* grid, const cav_halo* halo, const void* q,
+              void* buf, size_t buf_bytes, hipStream_t stream);
+
+/* Scatter buf back into the ghost boxes of the receiving subdomains (the
+ * unpack of Sec. 4.5).  With all subdomains in one array the receiver's
+ * ghost box beyond a face is the sender's box, so
+ * halo_unpack(halo_pack(q)) leaves q bit-identical.  One kernel launch.
+ * buf: device, read.  q: device, written on the segment cells only. */
+int halo_unpack(const cav_grid* grid, const cav_halo* halo, const void* buf,
+                size_t buf_bytes, void* q, hipStream_t stream);
+
+/* Residual L2 norms of the last step run by cavity_step on this ws:
+ * out5[f] = sqrt(sum over interior cells of R_f^2 / (ni*nj*nk)), f in
+ * p,u,v,w,T order (Sec. 4.2 mentions residual norms, printed outside the
+ * timed runs).  Reduced in FP64 in a fixed order (run-to-run identical).
+ * out5: HOST, 5 doubles.  Waits for `stream`.  Returns CAV_ENONFINITE if
+ * any norm is NaN or infinite (the values are still written). */
+int cavity_residual_norm(const cav_grid* grid, const void* ws, size_t ws_bytes,
+                         double* out5, hipStream_t stream);
+
+/* Discrete adjoint of one step (reverse mode) -- not available in this
+ * build: always returns CAV_ENOSYS and enqueues nothing. */
+int cavity_adjoint_step(const cav_grid* grid, const cav_params* prm,
+                        const void* q_n, const void* lam_in, void* lam_out,
+                        void* ws, size_t ws_bytes, double* dj_dthot,
+                        double* dj_dra, hipStream_t stream);
+
+/* Thread-local description of the last error returned on this thread. */
+const char* cavity_last_error(void);
+
+/* ---- per-kernel timing (measurement support) ---------------------------
+ * While enabled, every kernel the library launches is bracketed by a pair
+ * of HIP events recorded on the stream the kernel is launched on.
+ * cavity_timing_read waits for those events, returns per-kernel totals
+ * (at most max_entries, names as in the rocprofv3 kernel trace prefix)
+ * and clears them. */
+typedef struct {
+    char    name[32];
+    int64_t launches;
+    double  total_ms;
+} cav_kernel_time;
+
+int cavity_timing_enable(int32_t on);
+int cavity_timing_read(cav_kernel_time* out, int32_t max_entries, int32_t* n_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAVITY_H_ */

@@ -1,0 +1,140 @@
+"""Pins of the oracle's halo pack/unpack (Sec. 4.5, Listings 1-2) on the CPU.
+
+The buffer is checked against a brute-force gather written from the layout
+definition with numpy slicing, against the index formulas printed in
+Listing 1 (two layers of every field on an i face) and Listing 2 (pressure
+with two layers first, then the other fields with one layer), and for the
+round trip unpack(pack(q)) == q, also after poisoning every segment cell.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+NG = O.NG
+FACES = ((0, 0), (0, 1), (1, 0), (1, 1), (2, 0), (2, 1))   # (axis, high) for -x,+x,-y,+y,-z,+z
+
+
+def brute_gather(P, halo, q):
+    split, width = halo
+    n = (P.ni, P.nj, P.nk)
+    e = [n[d] // split[d] for d in range(3)]
+    out = []
+    for c in range(split[2]):
+        for b in range(split[1]):
+            for a in range(split[0]):
+                coord = (a, b, c)
+                for axis, high in FACES:
+                    if (not high and coord[axis] == 0) or (high and coord[axis] == split[axis] - 1):
+                        continue
+                    for f in range(5):
+                        w = width[f]
+                        if w == 0:
+                            continue
+                        lo = [coord[d] * e[d] for d in range(3)]
+                        hi = [(coord[d] + 1) * e[d] for d in range(3)]
+                        if high:
+                            lo[axis] = hi[axis] - w
+                        else:
+                            hi[axis] = lo[axis] + w
+                        box = q[f, NG + lo[2]:NG + hi[2], NG + lo[1]:NG + hi[1], NG + lo[0]:NG + hi[0]]
+                        out.append(box.reshape(-1))
+    return np.concatenate(out) if out else np.zeros(0)
+
+
+def splits_of(n):
+    return [s for s in itertools.product(range(1, 9), repeat=3)
+            if np.prod(s) <= 8 and all(n[d] % s[d] == 0 for d in range(3))]
+
+
+WIDTHS = [(2, 2, 2, 2, 2), (2, 1, 1, 1, 1), (1, 2, 2, 2, 2), (0, 1, 0, 2, 1), (1, 1, 1, 1, 1)]
+
+
+@pytest.mark.parametrize("n", [(8, 8, 8), (16, 8, 4), (12, 6, 10)])
+def test_pack_matches_brute_force(orc, n):
+    P = O.Problem(*n)
+    q = np.random.default_rng(0).standard_normal(P.shape)
+    for split in splits_of(n):
+        for width in WIDTHS:
+            if any(n[d] // split[d] < max(width) for d in range(3)):
+                continue
+            halo = (split, width)
+            buf = O.halo_pack(P, halo, q)
+            ref = brute_gather(P, halo, q)
+            assert buf.size == ref.size == O.halo_elems(P, halo)
+            assert np.array_equal(buf, ref), (split, width)
+
+
+def test_element_count_closed_form(orc):
+    """Count = sum over cut interfaces of width * face area: each of the
+    (Pi-1) i-cuts carries two directions of (nj*nk) * sum(width) values."""
+    P = O.Problem(16, 12, 8)
+    for split in ((8, 1, 1), (4, 2, 1), (2, 2, 2), (1, 3, 4), (16, 1, 1)):
+        for width in WIDTHS:
+            Pi, Pj, Pk = split
+            W = sum(width)
+            expect = W * 2 * ((Pi - 1) * P.nj * P.nk + (Pj - 1) * P.ni * P.nk + (Pk - 1) * P.ni * P.nj)
+            if min(P.ni // Pi, P.nj // Pj, P.nk // Pk) < max(width):
+                continue
+            assert O.halo_elems(P, (split, width)) == expect
+
+
+def test_listing1_index_order(orc):
+    """Listing 1: the -x face buffer of a block holds, for var = 0..4,
+    k, j over the face and i = 0, 1 the first two interior layers, at
+    index var*k_nodes*j_nodes*2 + k*j_nodes*2 + j*2 + i (0-based)."""
+    ni, nj, nk = 8, 5, 3
+    P = O.Problem(ni, nj, nk)
+    q = np.random.default_rng(1).standard_normal(P.shape)
+    buf = O.halo_pack(P, ((2, 1, 1), (2, 2, 2, 2, 2)), q)
+    seg = buf.size // 2                  # subdomain 0 sends +x, subdomain 1 sends -x
+    back = buf[seg:]                     # the -x face of the high block
+    x0 = ni // 2
+    for var in range(5):
+        for k in range(nk):
+            for j in range(nj):
+                for i in range(2):
+                    indx = var * nk * nj * 2 + k * nj * 2 + j * 2 + i
+                    assert back[indx] == q[var, NG + k, NG + j, NG + x0 + i]
+
+
+def test_listing2_stencil_widths(orc):
+    """Listing 2: pressure with two layers first (index k*j_nodes*2 + j*2
+    + i), then u, v, w, T with the first interior layer only, offset by
+    indx_p = k_nodes*j_nodes*2, at (var-2)*k_nodes*j_nodes + k*j_nodes + j
+    (var = 2..5 in the listing's 1-based numbering)."""
+    ni, nj, nk = 6, 4, 5
+    P = O.Problem(ni, nj, nk)
+    q = np.random.default_rng(2).standard_normal(P.shape)
+    buf = O.halo_pack(P, ((2, 1, 1), (2, 1, 1, 1, 1)), q)
+    back = buf[buf.size // 2:]
+    x0 = ni // 2
+    indx_p = nk * nj * 2
+    for k in range(nk):
+        for j in range(nj):
+            for i in range(2):
+                assert back[k * nj * 2 + j * 2 + i] == q[0, NG + k, NG + j, NG + x0 + i]
+            for var in range(2, 6):
+                indx = (var - 2) * nk * nj + k * nj + j
+                assert back[indx_p + indx] == q[var - 1, NG + k, NG + j, NG + x0]
+
+
+@pytest.mark.parametrize("split,width", [((2, 2, 2), (1, 2, 2, 2, 2)), ((8, 1, 1), (2, 1, 1, 1, 1)),
+                                         ((1, 4, 2), (2, 2, 2, 2, 2))])
+def test_unpack_round_trip_and_poison(orc, split, width):
+    P = O.Problem(16)
+    halo = (split, width)
+    q = np.random.default_rng(3).standard_normal(P.shape)
+    q0 = q.copy()
+    buf = O.halo_pack(P, halo, q)
+    O.halo_unpack(P, halo, buf, q)
+    assert np.array_equal(q, q0)
+    # poison every segment cell, then unpack restores them bit for bit
+    mark = np.zeros(P.shape)
+    O.halo_unpack(P, halo, np.ones(buf.size), mark)
+    assert 0 < mark.sum() <= buf.size   # boxes of one sender may share corner cells
+    q[mark == 1] = np.nan
+    O.halo_unpack(P, halo, buf, q)
+    assert np.array_equal(q, q0)
