@@ -1,0 +1,228 @@
+"""MI355X cavity library: Python binding of libcavity.so (include/cavity.h).
+
+The functions below carry the C ABI's names and only marshal arguments:
+torch tensors provide device memory and the current HIP stream, every step
+of the computation runs in the library's HIP kernels.  Nothing here falls
+back to a CPU implementation; if the library is missing, the first call
+raises ImportError.
+
+The solver is the explicit pseudo-time sweep of the 3D buoyancy-driven
+cavity of Xue & Roy (arXiv:2006.02602, Sec. 2-3) with the in-device halo
+pack/unpack of its "Optimized V1-V3" versions (Sec. 4.5).
+"""
+import ctypes
+from dataclasses import dataclass, field
+from typing import Optional, Sequence, Tuple
+
+from ._lib import (CAV_EHIP, CAV_EINVAL, CAV_ENONFINITE, CAV_ENOSYS, CAV_ESIZE, CAV_F64, CAV_OK,
+                   EXPORTS, CavError, CavGrid, CavHalo, CavKernelTime, CavParams, check, lib)
+
+NG = 2
+FIELDS = ("p", "u", "v", "w", "T")
+
+
+@dataclass(frozen=True)
+class Grid:
+    ni: int
+    nj: int
+    nk: int
+    ng: int = NG
+    dtype: int = CAV_F64
+
+    @staticmethod
+    def cube(n: int) -> "Grid":
+        return Grid(n, n, n)
+
+    def c(self) -> CavGrid:
+        return CavGrid(self.ni, self.nj, self.nk, self.ng, self.dtype)
+
+    @property
+    def shape(self) -> Tuple[int, int, int, int]:
+        return (5, self.nk + 2 * self.ng, self.nj + 2 * self.ng, self.ni + 2 * self.ng)
+
+    @property
+    def ncell(self) -> int:
+        return self.ni * self.nj * self.nk
+
+
+@dataclass(frozen=True)
+class Params:
+    """Nondimensional problem parameters (Sec. 2); see include/cavity.h."""
+    Ra: float = 1e3
+    Pr: float = 0.71
+    cfl: float = 0.5
+    eps4: float = 1.0 / 16
+    kappa: float = 0.25
+    u_ref: float = 1.0
+    t_hot: float = 1.0
+    t_cold: float = 0.0
+    t_inf: float = 0.5
+
+    def c(self) -> CavParams:
+        return CavParams(self.Ra, self.Pr, self.cfl, self.eps4, self.kappa, self.u_ref,
+                         self.t_hot, self.t_cold, self.t_inf, None)
+
+
+@dataclass(frozen=True)
+class Halo:
+    """Virtual split (Pi, Pj, Pk) and ghost width per field p, u, v, w, T."""
+    split: Tuple[int, int, int] = (2, 2, 2)
+    width: Tuple[int, int, int, int, int] = (1, 2, 2, 2, 2)
+
+    def c(self) -> CavHalo:
+        return CavHalo((ctypes.c_int32 * 3)(*self.split), (ctypes.c_int32 * 5)(*self.width))
+
+
+def _ptr(t):
+    """Device pointer and byte size of a tensor (or (ptr, nbytes) pair)."""
+    if t is None:
+        return None, 0
+    if isinstance(t, tuple):
+        return t
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr(), t.numel() * t.element_size()
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _grid(g):
+    return g.c() if isinstance(g, Grid) else g
+
+
+def _halo(h):
+    if h is None:
+        return None
+    return h.c() if isinstance(h, Halo) else h
+
+
+def _params(p):
+    return p.c() if isinstance(p, Params) else p
+
+
+# ---- the C ABI, name for name ------------------------------------------------
+
+def cavity_state_elems(grid) -> int:
+    return int(lib().cavity_state_elems(ctypes.byref(_grid(grid))))
+
+
+def cavity_workspace_bytes(grid) -> int:
+    return int(lib().cavity_workspace_bytes(ctypes.byref(_grid(grid))))
+
+
+def halo_buffer_bytes(grid, halo) -> int:
+    return int(lib().halo_buffer_bytes(ctypes.byref(_grid(grid)), ctypes.byref(_halo(halo))))
+
+
+def cavity_init(grid, params, seed: int, noise_amp: float, q, stream=None) -> None:
+    qp, _ = _ptr(q)
+    check(lib().cavity_init(ctypes.byref(_grid(grid)), ctypes.byref(_params(params)),
+                            ctypes.c_uint64(seed), float(noise_amp), qp, _stream(stream)))
+
+
+def cavity_step(grid, params, halo, q, q_tmp, ws, halo_buf, nsteps: int, stream=None) -> None:
+    qp, _ = _ptr(q)
+    tp, _ = _ptr(q_tmp)
+    wp, wb = _ptr(ws)
+    bp, bb = _ptr(halo_buf)
+    h = _halo(halo)
+    check(lib().cavity_step(ctypes.byref(_grid(grid)), ctypes.byref(_params(params)),
+                            ctypes.byref(h) if h is not None else None, qp, tp, wp, wb, bp, bb,
+                            int(nsteps), _stream(stream)))
+
+
+def halo_pack(grid, halo, q, buf, stream=None) -> None:
+    qp, _ = _ptr(q)
+    bp, bb = _ptr(buf)
+    check(lib().halo_pack(ctypes.byref(_grid(grid)), ctypes.byref(_halo(halo)), qp, bp, bb,
+                          _stream(stream)))
+
+
+def halo_unpack(grid, halo, buf, q, stream=None) -> None:
+    qp, _ = _ptr(q)
+    bp, bb = _ptr(buf)
+    check(lib().halo_unpack(ctypes.byref(_grid(grid)), ctypes.byref(_halo(halo)), bp, bb, qp,
+                            _stream(stream)))
+
+
+def cavity_residual_norm(grid, ws, stream=None):
+    """The last step's residual L2 norms (p, u, v, w, T) as a list of floats."""
+    wp, wb = _ptr(ws)
+    out = (ctypes.c_double * 5)()
+    check(lib().cavity_residual_norm(ctypes.byref(_grid(grid)), wp, wb, out, _stream(stream)))
+    return [out[i] for i in range(5)]
+
+
+def cavity_adjoint_step(grid, params, q_n, lam_in, lam_out, ws, dj_dthot, dj_dra, stream=None) -> None:
+    ptrs = [_ptr(t)[0] for t in (q_n, lam_in, lam_out)]
+    wp, wb = _ptr(ws)
+    check(lib().cavity_adjoint_step(ctypes.byref(_grid(grid)), ctypes.byref(_params(params)),
+                                    ptrs[0], ptrs[1], ptrs[2], wp, wb, _ptr(dj_dthot)[0],
+                                    _ptr(dj_dra)[0], _stream(stream)))
+
+
+def cavity_last_error() -> str:
+    return lib().cavity_last_error().decode(errors="replace")
+
+
+def cavity_timing_enable(on: bool) -> None:
+    check(lib().cavity_timing_enable(1 if on else 0))
+
+
+def cavity_timing_read():
+    """{kernel name: (launches, total ms)} recorded since the last read."""
+    arr = (CavKernelTime * 32)()
+    n = ctypes.c_int32(0)
+    check(lib().cavity_timing_read(arr, 32, ctypes.byref(n)))
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms))
+            for i in range(min(n.value, 32))}
+
+
+# ---- convenience: buffers for one cavity ------------------------------------
+
+class Cavity:
+    """Allocates the state, scratch state, workspace and halo buffer of one
+    cavity with torch and drives the C ABI on the current stream."""
+
+    def __init__(self, grid: Grid, params: Params = Params(), halo: Optional[Halo] = None,
+                 device: str = "cuda"):
+        import torch
+        self.grid, self.params, self.halo = grid, params, halo
+        n = cavity_state_elems(grid)
+        if n == 0:
+            raise CavError(CAV_EINVAL, cavity_last_error())
+        self.q = torch.zeros(n, dtype=torch.float64, device=device)
+        self.q_tmp = torch.zeros(n, dtype=torch.float64, device=device)
+        self.ws = torch.zeros(cavity_workspace_bytes(grid) // 8, dtype=torch.float64, device=device)
+        nb = halo_buffer_bytes(grid, halo) if halo is not None else 0
+        self.buf = torch.zeros(max(1, nb // 8), dtype=torch.float64, device=device) if halo is not None else None
+
+    def init(self, seed: int, noise_amp: float = 1e-3) -> "Cavity":
+        cavity_init(self.grid, self.params, seed, noise_amp, self.q)
+        return self
+
+    def step(self, nsteps: int) -> "Cavity":
+        cavity_step(self.grid, self.params, self.halo, self.q, self.q_tmp, self.ws, self.buf, nsteps)
+        return self
+
+    def norms(self):
+        return cavity_residual_norm(self.grid, self.ws)
+
+    def fields(self):
+        """The state as a (5, nk+4, nj+4, ni+4) view."""
+        return self.q.view(*self.grid.shape)
+
+    def interior(self):
+        g = self.grid.ng
+        return self.fields()[:, g:g + self.grid.nk, g:g + self.grid.nj, g:g + self.grid.ni]
+
+
+__all__ = ["Grid", "Params", "Halo", "Cavity", "CavError", "FIELDS", "NG", "EXPORTS",
+           "CAV_OK", "CAV_EINVAL", "CAV_ESIZE", "CAV_EHIP", "CAV_ENONFINITE", "CAV_ENOSYS"] + list(EXPORTS)

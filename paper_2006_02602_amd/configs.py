@@ -1,0 +1,46 @@
+"""Workload definitions: seeded synthetic cavities shaped like the paper's runs.
+
+The paper times its buoyancy-driven-cavity code on 256^3 meshes at Ra = 1e5
+(Sec. 2; Tables 3-4), meshes 32^3..1024^3, with 1D/2D/3D decompositions
+(Sec. 3.2).  There is no dataset: every input is the seeded initial state of
+include/cavity.h (fluid at rest up to +-noise, T linear between the walls).
+"""
+from dataclasses import dataclass
+from typing import Tuple
+
+from . import Grid, Halo, Params
+
+CONFIG_WIDTHS = (1, 2, 2, 2, 2)    # p 1 layer; u, v, w, T 2 layers
+PAPER_WIDTHS = (2, 1, 1, 1, 1)     # stencil-based widths of "Optimized V2" (Listing 2)
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    n: int
+    Ra: float
+    steps: int
+    seed: int
+    splits: Tuple[Tuple[int, int, int], ...]
+    widths: Tuple[int, int, int, int, int] = CONFIG_WIDTHS
+    noise: float = 1e-3
+
+    @property
+    def grid(self) -> Grid:
+        return Grid.cube(self.n)
+
+    @property
+    def params(self) -> Params:
+        return Params(Ra=self.Ra, Pr=0.71, cfl=0.5)
+
+    def halo(self, split=None, widths=None) -> Halo:
+        return Halo(split or self.splits[0], widths or self.widths)
+
+
+# small parity case: 16^3, Ra 1e3, 100 steps, 2x2x2 virtual split every step
+C0 = Workload("cavity16_f64_ra1e3", 16, 1e3, 100, 1, ((2, 2, 2),))
+# one GPU's share at the paper's size: 256^3, Ra 1e5, 200 steps; the headline
+# step exchanges the 3D (2,2,2) split; 1D (8,1,1) and 2D (4,2,1) are timed too
+C1 = Workload("cavity256_f64_ra1e5", 256, 1e5, 200, 2, ((2, 2, 2), (8, 1, 1), (4, 2, 1)))
+
+WORKLOADS = {w.name: w for w in (C0, C1)}

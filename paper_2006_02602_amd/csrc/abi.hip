@@ -1,0 +1,397 @@
+// Host side of the C ABI declared in include/cavity.h: argument checks (pure
+// host code, run before anything is enqueued), launch geometry, the step
+// loop, error reporting and the optional per-kernel event timing.
+#include "cavity.h"
+#include "cavity_internal.h"
+
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace cav;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+// ---- per-kernel event timing ---------------------------------------------
+struct TimeRec {
+    const char* name;
+    hipEvent_t a, b;
+};
+std::atomic<bool> g_timing{false};
+std::mutex g_tm;
+std::vector<TimeRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t take_event()
+{
+    std::lock_guard<std::mutex> lk(g_tm);
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+template <class F>
+hipError_t run(const char* name, hipStream_t s, F&& launch)
+{
+    if (!g_timing.load(std::memory_order_relaxed)) return launch();
+    hipEvent_t a = take_event(), b = take_event();
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, s);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_tm);
+    g_recs.push_back({name, a, b});
+    return e;
+}
+
+int hip_fail(const char* what, hipError_t e)
+{
+    return fail(CAV_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---- argument checks ------------------------------------------------------
+int check_grid(const cav_grid* g)
+{
+    if (!g) return fail(CAV_EINVAL, "grid is NULL");
+    if (g->ng != NG) return fail(CAV_EINVAL, "ng must be %d (got %d)", NG, g->ng);
+    if (g->dtype != CAV_F64) return fail(CAV_EINVAL, "unknown dtype %d", g->dtype);
+    if (g->ni < 2 || g->nj < 2 || g->nk < 2)
+        return fail(CAV_EINVAL, "every grid extent must be >= 2 (got %d x %d x %d)", g->ni, g->nj, g->nk);
+    const long long per = (long long)(g->ni + 2 * NG) * (g->nj + 2 * NG) * (g->nk + 2 * NG);
+    if (per >= (1LL << 31))
+        return fail(CAV_EINVAL, "grid %d x %d x %d too large (one field must stay below 2^31 elements)",
+                    g->ni, g->nj, g->nk);
+    return CAV_OK;
+}
+
+Dims dims_of(const cav_grid* g)
+{
+    Dims d;
+    d.ni = g->ni;
+    d.nj = g->nj;
+    d.nk = g->nk;
+    d.sy = g->ni + 2 * NG;
+    d.sz = (g->nj + 2 * NG) * d.sy;
+    return d;
+}
+
+size_t field_elems(const Dims& d) { return (size_t)(d.nk + 2 * NG) * (size_t)d.sz; }
+
+State state_of(void* q, const Dims& d)
+{
+    State s;
+    double* base = static_cast<double*>(q);
+    for (int f = 0; f < NF; ++f) s.f[f] = base + (size_t)f * field_elems(d);
+    return s;
+}
+
+CState cstate_of(const void* q, const Dims& d)
+{
+    CState s;
+    const double* base = static_cast<const double*>(q);
+    for (int f = 0; f < NF; ++f) s.f[f] = base + (size_t)f * field_elems(d);
+    return s;
+}
+
+int check_params(const cav_params* p)
+{
+    if (!p) return fail(CAV_EINVAL, "params is NULL");
+    const double v[9] = {p->Ra, p->Pr, p->cfl, p->eps4, p->kappa, p->u_ref, p->t_hot, p->t_cold, p->t_inf};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(CAV_EINVAL, "params must be finite");
+    if (!(p->Ra > 0) || !(p->Pr > 0)) return fail(CAV_EINVAL, "Ra and Pr must be > 0");
+    if (!(p->cfl > 0)) return fail(CAV_EINVAL, "cfl must be > 0");
+    if (p->eps4 < 0 || p->kappa < 0 || p->u_ref < 0)
+        return fail(CAV_EINVAL, "eps4, kappa and u_ref must be >= 0");
+    if (p->t_hot_field) return fail(CAV_EINVAL, "t_hot_field is not supported by this build (pass NULL)");
+    return CAV_OK;
+}
+
+Coef coef_of(const cav_grid* g, const cav_params* p)
+{
+    Coef c;
+    const double nx = g->ni, ny = g->nj, nz = g->nk;
+    c.hx2 = 0.5 * nx; c.hy2 = 0.5 * ny; c.hz2 = 0.5 * nz;
+    c.ix2 = nx * nx; c.iy2 = ny * ny; c.iz2 = nz * nz;
+    c.nx = nx; c.ny = ny; c.nz = nz;
+    c.eps4 = p->eps4;
+    c.beta2_floor = p->kappa * p->u_ref * p->u_ref;
+    c.nu = std::sqrt(p->Pr / p->Ra);
+    c.alpha = 1.0 / std::sqrt(p->Ra * p->Pr);
+    c.t_inf = p->t_inf;
+    c.cfl = p->cfl;
+    const double dmax = c.nu > c.alpha ? c.nu : c.alpha;
+    c.dt_visc = 1.0 / (2.0 * dmax * (nx * nx + ny * ny + nz * nz));
+    return c;
+}
+
+int check_halo(const cav_grid* g, const cav_halo* h, HaloGeom* out)
+{
+    if (!h) return fail(CAV_EINVAL, "halo is NULL");
+    const int n[3] = {g->ni, g->nj, g->nk};
+    HaloGeom hg;
+    long long nsub = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (h->split[a] < 1) return fail(CAV_EINVAL, "split[%d] = %d must be >= 1", a, h->split[a]);
+        if (n[a] % h->split[a])
+            return fail(CAV_EINVAL, "split[%d] = %d does not divide the grid extent %d", a, h->split[a], n[a]);
+        hg.P[a] = h->split[a];
+        hg.e[a] = n[a] / h->split[a];
+        nsub *= h->split[a];
+    }
+    if (nsub * 6 > 65535) return fail(CAV_EINVAL, "too many subdomains (%lld)", nsub);
+    int wmax = 0;
+    hg.wsum = 0;
+    for (int f = 0; f < NF; ++f) {
+        const int w = h->width[f];
+        if (w < 0 || w > g->ng) return fail(CAV_EINVAL, "width[%d] = %d outside [0, ng=%d]", f, w, g->ng);
+        hg.w[f] = w;
+        hg.wpre[f] = hg.wsum;
+        hg.wsum += w;
+        wmax = w > wmax ? w : wmax;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (hg.P[a] > 1 && hg.e[a] < wmax)
+            return fail(CAV_EINVAL, "subdomain extent %d along axis %d is thinner than width %d", hg.e[a], a, wmax);
+    hg.area[0] = (long long)hg.e[1] * hg.e[2];
+    hg.area[1] = (long long)hg.e[0] * hg.e[2];
+    hg.area[2] = (long long)hg.e[0] * hg.e[1];
+    long long amax = 0;
+    for (int a = 0; a < 3; ++a)
+        if (hg.P[a] > 1 && hg.area[a] > amax) amax = hg.area[a];
+    hg.face_blocks = (int)((amax + 255) / 256);
+    if (out) *out = hg;
+    return CAV_OK;
+}
+
+size_t halo_elems(const HaloGeom& h)
+{
+    const long long nsub = (long long)h.P[0] * h.P[1] * h.P[2];
+    long long faces_area = 0;
+    for (int a = 0; a < 3; ++a) faces_area += h.area[a] * 2LL * (h.P[a] - 1) * (nsub / h.P[a]);
+    return (size_t)(faces_area * h.wsum);
+}
+
+constexpr size_t WS_HEAD = 64;   // 5 final norms, padded
+
+size_t ws_bytes_of(const Dims& d)
+{
+    const SweepGeom g = sweep_geom(d);
+    return WS_HEAD + (size_t)g.nblocks * NF * sizeof(double);
+}
+
+int do_halo(const cav_grid* grid, const HaloGeom& hg, void* q, void* buf, bool pack, hipStream_t s)
+{
+    if (hg.face_blocks == 0 || hg.wsum == 0) return CAV_OK;       // nothing to exchange
+    const Dims d = dims_of(grid);
+    hipError_t e = run(pack ? "halo_pack" : "halo_unpack", s,
+                       [&] { return launch_halo(d, hg, state_of(q, d), static_cast<double*>(buf), pack, s); });
+    return e == hipSuccess ? CAV_OK : hip_fail(pack ? "halo_pack launch" : "halo_unpack launch", e);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t cavity_state_elems(const cav_grid* grid)
+{
+    if (check_grid(grid) != CAV_OK) return 0;
+    return (size_t)NF * field_elems(dims_of(grid));
+}
+
+size_t cavity_workspace_bytes(const cav_grid* grid)
+{
+    if (check_grid(grid) != CAV_OK) return 0;
+    return ws_bytes_of(dims_of(grid));
+}
+
+size_t halo_buffer_bytes(const cav_grid* grid, const cav_halo* halo)
+{
+    HaloGeom hg;
+    if (check_grid(grid) != CAV_OK || check_halo(grid, halo, &hg) != CAV_OK) return 0;
+    return halo_elems(hg) * sizeof(double);
+}
+
+int cavity_init(const cav_grid* grid, const cav_params* prm, uint64_t seed, double noise_amp, void* q,
+                hipStream_t stream)
+{
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_params(prm))) return rc;
+    if (!q) return fail(CAV_EINVAL, "q is NULL");
+    if (!std::isfinite(noise_amp)) return fail(CAV_EINVAL, "noise_amp must be finite");
+    const Dims d = dims_of(grid);
+    const State s = state_of(q, d);
+    hipError_t e = run("init", stream, [&] { return launch_init(d, prm->t_hot, prm->t_cold, seed, noise_amp, s, stream); });
+    if (e != hipSuccess) return hip_fail("init launch", e);
+    const Bcs bc{prm->t_hot, prm->t_cold};
+    e = run("bc", stream, [&] { return launch_bc(d, bc, s, stream); });
+    if (e != hipSuccess) return hip_fail("bc launch", e);
+    return CAV_OK;
+}
+
+int cavity_step(const cav_grid* grid, const cav_params* prm, const cav_halo* halo, void* q, void* q_tmp,
+                void* ws, size_t ws_bytes, void* halo_buf, size_t halo_bytes, int32_t nsteps,
+                hipStream_t stream)
+{
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_params(prm))) return rc;
+    if (nsteps < 0) return fail(CAV_EINVAL, "nsteps = %d must be >= 0", nsteps);
+    if (!q || !q_tmp || !ws) return fail(CAV_EINVAL, "q, q_tmp and ws must not be NULL");
+    if (q == q_tmp) return fail(CAV_EINVAL, "q and q_tmp must be distinct buffers");
+    const Dims d = dims_of(grid);
+    const size_t need_ws = ws_bytes_of(d);
+    if (ws_bytes < need_ws) return fail(CAV_ESIZE, "ws_bytes %zu < required %zu", ws_bytes, need_ws);
+    HaloGeom hg;
+    if (halo) {
+        if ((rc = check_halo(grid, halo, &hg))) return rc;
+        const size_t need = halo_elems(hg) * sizeof(double);
+        if (need && !halo_buf) return fail(CAV_EINVAL, "halo_buf is NULL");
+        if (halo_bytes < need) return fail(CAV_ESIZE, "halo_bytes %zu < required %zu", halo_bytes, need);
+    }
+    if (nsteps == 0) return CAV_OK;
+
+    const Coef c = coef_of(grid, prm);
+    const SweepGeom g = sweep_geom(d);
+    const Bcs bc{prm->t_hot, prm->t_cold};
+    double* wsd = static_cast<double*>(ws);
+    double* partials = reinterpret_cast<double*>(static_cast<char*>(ws) + WS_HEAD);
+    void* cur = q;
+    void* nxt = q_tmp;
+    hipError_t e;
+    for (int n = 0; n < nsteps; ++n) {
+        const State sc = state_of(cur, d);
+        e = run("bc", stream, [&] { return launch_bc(d, bc, sc, stream); });
+        if (e != hipSuccess) return hip_fail("bc launch", e);
+        if (halo) {
+            if ((rc = do_halo(grid, hg, cur, halo_buf, true, stream))) return rc;
+            if ((rc = do_halo(grid, hg, cur, halo_buf, false, stream))) return rc;
+        }
+        const bool last = n == nsteps - 1;
+        e = run(last ? "sweep_norm" : "sweep", stream, [&] {
+            return launch_sweep(d, c, g, cstate_of(cur, d), state_of(nxt, d), partials, last, stream);
+        });
+        if (e != hipSuccess) return hip_fail("sweep launch", e);
+        void* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    const double ncell = (double)d.ni * d.nj * d.nk;
+    e = run("norm_finalize", stream, [&] { return launch_norm_finalize(partials, g.nblocks, ncell, wsd, stream); });
+    if (e != hipSuccess) return hip_fail("norm finalize launch", e);
+    if (cur != q) {
+        const size_t bytes = (size_t)NF * field_elems(d) * sizeof(double);
+        e = run("copy", stream, [&] { return hipMemcpyAsync(q, cur, bytes, hipMemcpyDeviceToDevice, stream); });
+        if (e != hipSuccess) return hip_fail("state copy", e);
+    }
+    return CAV_OK;
+}
+
+int halo_pack(const cav_grid* grid, const cav_halo* halo, const void* q, void* buf, size_t buf_bytes,
+              hipStream_t stream)
+{
+    int rc;
+    HaloGeom hg;
+    if ((rc = check_grid(grid)) || (rc = check_halo(grid, halo, &hg))) return rc;
+    const size_t need = halo_elems(hg) * sizeof(double);
+    if (!q || (need && !buf)) return fail(CAV_EINVAL, "q and buf must not be NULL");
+    if (buf_bytes < need) return fail(CAV_ESIZE, "buf_bytes %zu < required %zu", buf_bytes, need);
+    return do_halo(grid, hg, const_cast<void*>(q), buf, true, stream);
+}
+
+int halo_unpack(const cav_grid* grid, const cav_halo* halo, const void* buf, size_t buf_bytes, void* q,
+                hipStream_t stream)
+{
+    int rc;
+    HaloGeom hg;
+    if ((rc = check_grid(grid)) || (rc = check_halo(grid, halo, &hg))) return rc;
+    const size_t need = halo_elems(hg) * sizeof(double);
+    if (!q || (need && !buf)) return fail(CAV_EINVAL, "q and buf must not be NULL");
+    if (buf_bytes < need) return fail(CAV_ESIZE, "buf_bytes %zu < required %zu", buf_bytes, need);
+    return do_halo(grid, hg, q, const_cast<void*>(buf), false, stream);
+}
+
+int cavity_residual_norm(const cav_grid* grid, const void* ws, size_t ws_bytes, double* out5, hipStream_t stream)
+{
+    int rc;
+    if ((rc = check_grid(grid))) return rc;
+    if (!ws || !out5) return fail(CAV_EINVAL, "ws and out5 must not be NULL");
+    const size_t need = ws_bytes_of(dims_of(grid));
+    if (ws_bytes < need) return fail(CAV_ESIZE, "ws_bytes %zu < required %zu", ws_bytes, need);
+    hipError_t e = hipMemcpyAsync(out5, ws, NF * sizeof(double), hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return hip_fail("norm copy", e);
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail("stream synchronize", e);
+    for (int f = 0; f < NF; ++f)
+        if (!std::isfinite(out5[f])) return fail(CAV_ENONFINITE, "residual norm of field %d is not finite", f);
+    return CAV_OK;
+}
+
+int cavity_adjoint_step(const cav_grid*, const cav_params*, const void*, const void*, void*, void*, size_t,
+                        double*, double*, hipStream_t)
+{
+    return fail(CAV_ENOSYS, "cavity_adjoint_step is not available in this build");
+}
+
+const char* cavity_last_error(void) { return g_err; }
+
+int cavity_timing_enable(int32_t on)
+{
+    g_timing.store(on != 0);
+    return CAV_OK;
+}
+
+int cavity_timing_read(cav_kernel_time* out, int32_t max_entries, int32_t* n_out)
+{
+    if (max_entries < 0 || (max_entries > 0 && !out)) return fail(CAV_EINVAL, "bad output array");
+    std::lock_guard<std::mutex> lk(g_tm);
+    std::vector<cav_kernel_time> acc;
+    int rc = CAV_OK;
+    for (const TimeRec& r : g_recs) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) rc = hip_fail("event timing", e);
+        size_t k = 0;
+        while (k < acc.size() && std::strcmp(acc[k].name, r.name)) ++k;
+        if (k == acc.size()) {
+            cav_kernel_time t;
+            std::memset(&t, 0, sizeof t);
+            std::snprintf(t.name, sizeof t.name, "%s", r.name);
+            acc.push_back(t);
+        }
+        acc[k].launches += 1;
+        acc[k].total_ms += ms;
+        g_pool.push_back(r.a);
+        g_pool.push_back(r.b);
+    }
+    g_recs.clear();
+    const int n = (int)acc.size() < max_entries ? (int)acc.size() : max_entries;
+    for (int k = 0; k < n; ++k) out[k] = acc[k];
+    if (n_out) *n_out = (int32_t)acc.size();
+    return rc;
+}
+
+}  // extern "C"

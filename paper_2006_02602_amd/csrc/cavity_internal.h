@@ -1,0 +1,86 @@
+// Internal declarations shared by the library's own sources (host ABI and
+// kernels).  Not installed; the public interface is include/cavity.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cav {
+
+constexpr int NG = 2;       // ghost layers per side
+constexpr int NF = 5;       // fields p, u, v, w, T
+enum Field { FP = 0, FU = 1, FV = 2, FW = 3, FT = 4 };
+
+// Field base pointers of one state array plus its strides (elements).  Cell
+// offsets inside one field fit in 32 bits for every grid this library
+// accepts (checked by the host).
+struct State {
+    double* f[NF];
+};
+struct CState {
+    const double* f[NF];
+};
+
+struct Dims {
+    int ni, nj, nk;
+    int sy;     // ni + 2*NG
+    int sz;     // (nj + 2*NG) * sy
+};
+
+__host__ __device__ inline int cell_off(const Dims& d, int i, int j, int k)
+{
+    return (k + NG) * d.sz + (j + NG) * d.sy + (i + NG);
+}
+
+// Per-cell coefficients of the residual (all derived on the host).
+struct Coef {
+    double hx2, hy2, hz2;     // 1/(2h) = n/2 per axis
+    double ix2, iy2, iz2;     // 1/h^2 = n^2 per axis
+    double nx, ny, nz;        // 1/h = n per axis
+    double eps4;              // fourth-difference dissipation coefficient
+    double beta2_floor;       // kappa * u_ref^2
+    double nu, alpha;         // momentum and thermal diffusivities
+    double t_inf;             // buoyancy reference temperature
+    double cfl;
+    double dt_visc;           // 1 / (2 max(nu, alpha) (nx^2 + ny^2 + nz^2))
+};
+
+// Sweep launch geometry.
+constexpr int SW_TI = 64;     // tile width along i (one wavefront)
+constexpr int SW_TJ = 8;      // tile rows along j (one wavefront each)
+
+struct SweepGeom {
+    int tiles_i, tiles_j;     // tiles per plane
+    int kc;                   // k planes per block
+    int nkc;                  // k chunks
+    int nblocks;              // tiles_i * tiles_j * nkc
+};
+SweepGeom sweep_geom(const Dims& d);
+
+struct Bcs {
+    double t_hot, t_cold;
+};
+
+// Halo geometry (virtual split, widths) shared by pack and unpack.
+struct HaloGeom {
+    int P[3];                 // subdomains along i, j, k
+    int e[3];                 // subdomain extents
+    int w[NF];                // widths
+    int wsum;                 // sum of widths
+    int wpre[NF];             // exclusive prefix sums of widths
+    long long area[3];        // face area of an i, j, k face
+    int face_blocks;          // blocks per (subdomain, face)
+};
+
+// Launchers (return hipGetLastError() of the launch).
+hipError_t launch_bc(const Dims& d, const Bcs& b, State q, hipStream_t s);
+hipError_t launch_init(const Dims& d, double t_hot, double t_cold, uint64_t seed, double amp,
+                       State q, hipStream_t s);
+hipError_t launch_sweep(const Dims& d, const Coef& c, const SweepGeom& g, CState q, State qn,
+                        double* partials, bool with_norm, hipStream_t s);
+hipError_t launch_norm_finalize(const double* partials, int nblocks, double ncell, double* out,
+                                hipStream_t s);
+hipError_t launch_halo(const Dims& d, const HaloGeom& h, State q, double* buf, bool pack,
+                       hipStream_t s);
+
+}  // namespace cav

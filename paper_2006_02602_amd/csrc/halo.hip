@@ -1,0 +1,110 @@
+// In-device halo pack / unpack for gfx950 (Xue & Roy, arXiv:2006.02602,
+// Sec. 4.5: "Optimized V1" packs the noncontiguous i faces into a contiguous
+// buffer in parallel on the device, "V2" sends each field with its own
+// stencil width, "V3" extends the buffers to the j and k faces).
+//
+// One launch covers every (subdomain, face) pair of the virtual split:
+// blockIdx.y = subdomain * 6 + face, blockIdx.x walks the face's tangential
+// cells.  Each thread owns one tangential cell of the face and moves all
+// fields and layers of it, so the buffer position needs one integer
+// division per thread.  The buffer offset of a subdomain is a closed-form
+// prefix sum over the cut faces that precede it.
+//
+// Buffer layout: subdomains s = a + Pi*(b + Pj*c) in order; faces
+// -x, +x, -y, +y, -z, +z that are cuts; fields p, u, v, w, T with width > 0;
+// within a field the sender's box in (k, j, i) order, i fastest.
+#include "cavity_internal.h"
+
+namespace cav {
+
+// Cut faces along one axis among the first m of P subdomains.
+__device__ __forceinline__ long long cuts_before(int P, int m)
+{
+    return m == 0 ? 0 : (long long)(m - 1) + min(m, P - 1);
+}
+__device__ __forceinline__ int cuts_of(int P, int a)
+{
+    return (a > 0 ? 1 : 0) + (a < P - 1 ? 1 : 0);
+}
+
+template <bool PACK>
+__global__ __launch_bounds__(256) void halo_kernel(Dims d, HaloGeom h, State q, double* buf)
+{
+    const int slot = blockIdx.y;
+    const int s = slot / 6, face = slot - 6 * s;
+    const int Pi = h.P[0], Pj = h.P[1], Pk = h.P[2];
+    const int a = s % Pi, c = s / (Pi * Pj), b = (s / Pi) % Pj;
+    const int axis = face >> 1;
+    const bool high = face & 1;
+    const int coord = axis == 0 ? a : (axis == 1 ? b : c);
+    if (high ? coord == h.P[axis] - 1 : coord == 0) return;     // a cavity wall, not a cut
+
+    const int area = (int)h.area[axis];
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= area) return;
+
+    // offset (in tangential cells) of subdomain s, then of this face within s
+    const long long Ax = h.area[0], Ay = h.area[1], Az = h.area[2];
+    long long u = (long long)c * (Ax * 2LL * (Pi - 1) * Pj + Ay * 2LL * (Pj - 1) * Pi)
+                + Az * cuts_before(Pk, c) * Pi * Pj
+                + (long long)b * Ax * 2LL * (Pi - 1) + Ay * cuts_before(Pj, b) * Pi
+                + Az * cuts_of(Pk, c) * (long long)Pi * b
+                + Ax * cuts_before(Pi, a) + Ay * cuts_of(Pj, b) * (long long)a
+                + Az * cuts_of(Pk, c) * (long long)a;
+    const int cc[3] = {a, b, c};
+    for (int f2 = 0; f2 < face; ++f2) {
+        const int ax2 = f2 >> 1;
+        const bool hi2 = f2 & 1;
+        if (!(hi2 ? cc[ax2] == h.P[ax2] - 1 : cc[ax2] == 0)) u += h.area[ax2];
+    }
+    double* B = buf + u * h.wsum;
+
+    const int ex = h.e[0], ey = h.e[1], ez = h.e[2];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const int w = h.w[f];
+        if (w == 0) continue;
+        double* Bf = B + (long long)h.wpre[f] * area;
+        double* Q = q.f[f];
+        if (axis == 0) {
+            const int jj = t % ey, kk = t / ey;
+            const int gi = high ? (a + 1) * ex - w : a * ex;
+            const int o = cell_off(d, gi, b * ey + jj, c * ez + kk);
+            for (int l = 0; l < w; ++l) {
+                if (PACK) Bf[(long long)t * w + l] = Q[o + l];
+                else      Q[o + l] = Bf[(long long)t * w + l];
+            }
+        } else if (axis == 1) {
+            const int ii = t % ex, kk = t / ex;
+            const int gj = high ? (b + 1) * ey - w : b * ey;
+            const int o = cell_off(d, a * ex + ii, gj, c * ez + kk);
+            for (int l = 0; l < w; ++l) {
+                const long long x = ((long long)kk * w + l) * ex + ii;
+                if (PACK) Bf[x] = Q[o + l * d.sy];
+                else      Q[o + l * d.sy] = Bf[x];
+            }
+        } else {
+            const int ii = t % ex, jj = t / ex;
+            const int gk = high ? (c + 1) * ez - w : c * ez;
+            const int o = cell_off(d, a * ex + ii, b * ey + jj, gk);
+            for (int l = 0; l < w; ++l) {
+                const long long x = ((long long)l * ey + jj) * ex + ii;
+                if (PACK) Bf[x] = Q[o + l * d.sz];
+                else      Q[o + l * d.sz] = Bf[x];
+            }
+        }
+    }
+}
+
+hipError_t launch_halo(const Dims& d, const HaloGeom& h, State q, double* buf, bool pack, hipStream_t s)
+{
+    const int nsub = h.P[0] * h.P[1] * h.P[2];
+    dim3 grid(h.face_blocks, nsub * 6), block(256);
+    if (pack)
+        halo_kernel<true><<<grid, block, 0, s>>>(d, h, q, buf);
+    else
+        halo_kernel<false><<<grid, block, 0, s>>>(d, h, q, buf);
+    return hipGetLastError();
+}
+
+}  // namespace cav

@@ -1,0 +1,129 @@
+"""Host-side checks of the C ABI (CPU only: no call here reaches the GPU).
+
+The library must load, export every function include/cavity.h declares,
+size its buffers as the oracle counts them, and reject bad arguments with
+the documented error codes before it enqueues anything.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import oracle as O
+import paper_2006_02602_amd as C
+from paper_2006_02602_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cavity.h")
+FAKE = ctypes.c_void_p(0x1000)          # never dereferenced: every call below fails validation
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if not n.startswith("__")))
+
+
+def test_library_exports_every_declared_symbol():
+    decl = declared_functions()
+    assert set(decl) == set(_lib.EXPORTS), decl
+    L = C.lib()
+    for name in decl:
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
+    assert set(decl) <= exported
+
+
+def test_state_and_workspace_sizes():
+    for n in ((2, 2, 2), (16, 16, 16), (67, 37, 21), (256, 256, 256)):
+        g = C.Grid(*n)
+        assert C.cavity_state_elems(g) == 5 * (n[0] + 4) * (n[1] + 4) * (n[2] + 4)
+        assert C.cavity_workspace_bytes(g) >= 64 + 40
+
+
+@pytest.mark.parametrize("n", [(16, 16, 16), (24, 12, 20), (256, 256, 256)])
+def test_halo_bytes_match_oracle(orc, n):
+    P = O.Problem(*n)
+    g = C.Grid(*n)
+    for split in ((2, 2, 2), (8, 1, 1), (4, 2, 1), (1, 1, 1), (2, 3, 4), (3, 1, 2)):
+        for width in ((1, 2, 2, 2, 2), (2, 1, 1, 1, 1), (0, 0, 1, 0, 2), (0, 0, 0, 0, 0)):
+            if any(n[d] % split[d] for d in range(3)):
+                assert C.halo_buffer_bytes(g, C.Halo(split, width)) == 0
+                continue
+            assert C.halo_buffer_bytes(g, C.Halo(split, width)) == 8 * O.halo_elems(P, (split, width))
+
+
+def _step_rc(grid=None, params=None, halo=None, q=FAKE, q_tmp=ctypes.c_void_p(0x2000), ws=FAKE,
+             ws_bytes=1 << 30, buf=FAKE, buf_bytes=1 << 40, nsteps=1):
+    L = C.lib()
+    g = (grid or C.Grid(16, 16, 16)).c() if not isinstance(grid, _lib.CavGrid) else grid
+    p = (params or C.Params()).c() if not isinstance(params, _lib.CavParams) else params
+    h = halo.c() if isinstance(halo, C.Halo) else halo
+    return L.cavity_step(ctypes.byref(g), ctypes.byref(p), ctypes.byref(h) if h is not None else None,
+                         q, q_tmp, ws, ws_bytes, buf, buf_bytes, nsteps, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(grid=_lib.CavGrid(16, 16, 16, 3, 0)), C.CAV_EINVAL),          # ng != 2
+    (dict(grid=_lib.CavGrid(16, 16, 16, 2, 7)), C.CAV_EINVAL),          # dtype
+    (dict(grid=C.Grid(1, 16, 16)), C.CAV_EINVAL),                       # extent < 2
+    (dict(grid=C.Grid(2000, 2000, 2000)), C.CAV_EINVAL),                # 32-bit field offsets
+    (dict(params=C.Params(Ra=0.0)), C.CAV_EINVAL),
+    (dict(params=C.Params(cfl=-1.0)), C.CAV_EINVAL),
+    (dict(params=C.Params(Pr=float("nan"))), C.CAV_EINVAL),
+    (dict(halo=C.Halo((3, 1, 1), (1, 2, 2, 2, 2))), C.CAV_EINVAL),      # split does not divide
+    (dict(halo=C.Halo((0, 1, 1), (1, 2, 2, 2, 2))), C.CAV_EINVAL),
+    (dict(halo=C.Halo((2, 1, 1), (3, 2, 2, 2, 2))), C.CAV_EINVAL),      # width > ng
+    (dict(halo=C.Halo((2, 1, 1), (-1, 2, 2, 2, 2))), C.CAV_EINVAL),
+    (dict(halo=C.Halo((16, 1, 1), (1, 2, 2, 2, 2))), C.CAV_EINVAL),     # slices thinner than width
+    (dict(halo=C.Halo((2, 2, 2), (1, 2, 2, 2, 2)), buf_bytes=8), C.CAV_ESIZE),
+    (dict(halo=C.Halo((2, 2, 2), (1, 2, 2, 2, 2)), buf=None), C.CAV_EINVAL),
+    (dict(ws_bytes=16), C.CAV_ESIZE),
+    (dict(q=None), C.CAV_EINVAL),
+    (dict(ws=None), C.CAV_EINVAL),
+    (dict(q_tmp=FAKE), C.CAV_EINVAL),                                   # q == q_tmp
+    (dict(nsteps=-1), C.CAV_EINVAL),
+])
+def test_step_rejects_bad_arguments(kw, code):
+    assert _step_rc(**kw) == code
+    assert C.cavity_last_error()
+
+
+def test_step_zero_steps_is_a_no_op():
+    assert _step_rc(nsteps=0) == C.CAV_OK
+
+
+def test_t_hot_field_rejected():
+    p = C.Params().c()
+    p.t_hot_field = 0x1000
+    assert _step_rc(params=p) == C.CAV_EINVAL
+
+
+def test_pack_unpack_and_norm_validation():
+    L = C.lib()
+    g = C.Grid(16, 16, 16).c()
+    h = C.Halo((2, 2, 2), (1, 2, 2, 2, 2)).c()
+    need = C.halo_buffer_bytes(C.Grid(16, 16, 16), C.Halo())
+    assert L.halo_pack(ctypes.byref(g), ctypes.byref(h), FAKE, FAKE, need - 8, None) == C.CAV_ESIZE
+    assert L.halo_unpack(ctypes.byref(g), ctypes.byref(h), FAKE, need - 1, FAKE, None) == C.CAV_ESIZE
+    assert L.halo_pack(ctypes.byref(g), None, FAKE, FAKE, need, None) == C.CAV_EINVAL
+    assert L.halo_pack(ctypes.byref(g), ctypes.byref(h), None, FAKE, need, None) == C.CAV_EINVAL
+    out = (ctypes.c_double * 5)()
+    assert L.cavity_residual_norm(ctypes.byref(g), FAKE, 8, out, None) == C.CAV_ESIZE
+    assert L.cavity_residual_norm(ctypes.byref(g), None, 1 << 20, out, None) == C.CAV_EINVAL
+    assert L.cavity_init(None, None, 0, 0.0, FAKE, None) == C.CAV_EINVAL
+
+
+def test_adjoint_not_available():
+    with pytest.raises(C.CavError) as e:
+        C.cavity_adjoint_step(C.Grid(16, 16, 16), C.Params(), None, None, None, None, None, None, stream=0)
+    assert e.value.code == C.CAV_ENOSYS
+
+
+def test_timing_read_empty():
+    C.cavity_timing_enable(False)
+    assert C.cavity_timing_read() == {}

@@ -1,0 +1,247 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Pack/unpack and init must match bit for bit; the FP64 sweep must match the
+oracle within 1e-12 relative per field (max |gpu - oracle| / max |oracle|
+over the interior) after the configured number of steps.  At the full
+256^3 size the tests compare a few steps element by element and check
+properties that hold at any length (exact mirror symmetry, determinism).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+TOL_F64 = 1e-12
+NG = 2
+
+
+@pytest.fixture(scope="module")
+def C():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2006_02602_amd as C
+    C.lib()
+    return C
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a).reshape(-1)).cuda()
+
+
+def host(t, shape):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy().reshape(shape)
+
+
+def face_ghost_mask(shape):
+    """Interior plus the face ghost layers (no edge or corner ghosts)."""
+    _, K, J, I = shape
+    m = np.zeros((K, J, I), dtype=bool)
+    m[NG:K - NG, NG:J - NG, :] = True
+    m[NG:K - NG, :, NG:I - NG] = True
+    m[:, NG:J - NG, NG:I - NG] = True
+    return m
+
+
+def rel_err(a, b):
+    return [float(np.abs(a[f] - b[f]).max() / max(np.abs(b[f]).max(), 1e-300)) for f in range(5)]
+
+
+def problem(C, n, Ra=1e3, **kw):
+    P = O.Problem(*n, Ra=Ra, **kw)
+    g = C.Grid(*n)
+    prm = C.Params(Ra=Ra, Pr=P.Pr, cfl=P.cfl, eps4=P.eps4, kappa=P.kappa, u_ref=P.u_ref,
+                   t_hot=P.t_hot, t_cold=P.t_cold, t_inf=P.t_inf)
+    return P, g, prm
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [(16, 16, 16), (67, 37, 21), (2, 3, 2)])
+def test_init_bit_exact(C, n):
+    say("init", n)
+    P, g, prm = problem(C, n)
+    ref = O.init(P, 11, 1e-3)
+    cav = C.Cavity(g, prm).init(11, 1e-3)
+    got = host(cav.q, P.shape)
+    m = face_ghost_mask(P.shape)
+    for f in range(5):
+        assert np.array_equal(got[f][m], ref[f][m]), O.FIELDS[f]
+
+
+# ---------------------------------------------------------------------------
+PACK_CASES = [((16, 16, 16), (2, 2, 2), (1, 2, 2, 2, 2)),
+              ((16, 16, 16), (2, 2, 2), (2, 1, 1, 1, 1)),
+              ((30, 12, 21), (5, 3, 7), (2, 0, 1, 2, 1)),
+              ((64, 48, 40), (8, 1, 1), (1, 2, 2, 2, 2)),
+              ((256, 256, 256), (2, 2, 2), (1, 2, 2, 2, 2)),
+              ((256, 256, 256), (8, 1, 1), (1, 2, 2, 2, 2)),
+              ((256, 256, 256), (4, 2, 1), (1, 2, 2, 2, 2)),
+              ((256, 256, 256), (8, 1, 1), (2, 1, 1, 1, 1)),
+              ((256, 256, 256), (4, 2, 1), (2, 1, 1, 1, 1)),
+              ((256, 256, 256), (2, 2, 2), (2, 1, 1, 1, 1))]
+
+
+@pytest.mark.parametrize("n,split,width", PACK_CASES)
+def test_pack_unpack_bit_exact(C, n, split, width):
+    import torch
+    say("pack/unpack", n, split, width)
+    P = O.Problem(*n)
+    g, h = C.Grid(*n), C.Halo(split, width)
+    q = np.random.default_rng(hash((n, split, width)) % 2**32).standard_normal(P.shape)
+    ref = O.halo_pack(P, (split, width), q)
+    qd = dev(q)
+    nbytes = C.halo_buffer_bytes(g, h)
+    assert nbytes == 8 * ref.size
+    buf = torch.full((ref.size,), float("nan"), dtype=torch.float64, device="cuda")
+    C.halo_pack(g, h, qd, buf)
+    got = host(buf, ref.shape)
+    assert np.array_equal(got, ref)
+    # unpack into a copy whose segment cells are poisoned restores q exactly
+    mark = np.zeros(P.shape)
+    O.halo_unpack(P, (split, width), np.ones(ref.size), mark)
+    qp = q.copy()
+    qp[mark == 1] = np.nan
+    qpd = dev(qp)
+    C.halo_unpack(g, h, buf, qpd)
+    assert np.array_equal(host(qpd, P.shape), q)
+    # and the round trip leaves q bit-identical
+    C.halo_unpack(g, h, buf, qd)
+    assert np.array_equal(host(qd, P.shape), q)
+
+
+# ---------------------------------------------------------------------------
+def run_both(C, n, Ra, steps, seed, halo=None, noise=1e-3, **kw):
+    P, g, prm = problem(C, n, Ra=Ra, **kw)
+    q0 = O.init(P, seed, noise)
+    ref = q0.copy()
+    nref = O.step(P, ref, steps, halo=halo)
+    cav = C.Cavity(g, prm, C.Halo(*halo) if halo else None)
+    cav.q.copy_(dev(q0))
+    cav.step(steps)
+    got = host(cav.q, P.shape)
+    ngot = cav.norms()
+    return P, P.interior(got), P.interior(ref), np.array(ngot), nref
+
+
+def test_step_parity_small_config(C):
+    """16^3, Ra 1e3, 100 steps, 2x2x2 virtual split with widths p 1, others 2."""
+    say("step 16^3 x100")
+    P, a, b, na, nb = run_both(C, (16, 16, 16), 1e3, 100, 1, halo=((2, 2, 2), (1, 2, 2, 2, 2)))
+    e = rel_err(a, b)
+    say("rel err per field", e, "norms", na, nb)
+    assert max(e) <= TOL_F64, e
+    np.testing.assert_allclose(na, nb, rtol=TOL_F64, atol=0)
+
+
+@pytest.mark.parametrize("n,Ra,steps,halo", [
+    ((67, 37, 21), 1e4, 20, None),               # ragged in every tile direction
+    ((130, 9, 40), 1e5, 7, ((2, 3, 4), (2, 1, 1, 1, 1))),
+    ((2, 2, 2), 1e3, 10, None),                  # smallest grid
+    ((5, 64, 3), 1e6, 12, ((1, 4, 1), (1, 2, 2, 2, 2))),
+])
+def test_step_parity_ragged(C, n, Ra, steps, halo):
+    say("step", n, Ra, steps, halo)
+    P, a, b, na, nb = run_both(C, n, Ra, steps, 5, halo=halo)
+    e = rel_err(a, b)
+    say("rel err", e)
+    assert max(e) <= TOL_F64, e
+    np.testing.assert_allclose(na, nb, rtol=TOL_F64, atol=0)
+
+
+def test_step_parity_full_size(C):
+    """256^3, Ra 1e5 with the 3D split of the timed step: 3 steps compared
+    element by element (odd count: the result is copied back into q)."""
+    say("step 256^3 x3")
+    P, a, b, na, nb = run_both(C, (256, 256, 256), 1e5, 3, 2, halo=((2, 2, 2), (1, 2, 2, 2, 2)))
+    e = rel_err(a, b)
+    say("rel err", e, "norms", na, nb)
+    assert max(e) <= TOL_F64, e
+    np.testing.assert_allclose(na, nb, rtol=TOL_F64, atol=0)
+
+
+# ---------------------------------------------------------------------------
+def test_quiescent_rest_exact(C):
+    say("quiescent")
+    n = (20, 12, 9)
+    P, g, prm = problem(C, n, t_hot=0.5, t_cold=0.5, t_inf=0.5)
+    cav = C.Cavity(g, prm, C.Halo((2, 1, 1), (2, 1, 1, 1, 1))).init(3, 0.0)
+    cav.step(25)
+    I = host(cav.q, P.shape)
+    I = P.interior(I)
+    assert np.all(I[:4] == 0.0) and np.all(I[4] == 0.5)
+    assert cav.norms() == [0.0] * 5
+
+
+def y_symmetric_state(P, seed):
+    q = O.init(P, seed, 1e-3)
+    I = P.interior(q)
+    half = P.nj // 2
+    for f in range(5):
+        s = -1.0 if f == 2 else 1.0
+        I[f][:, P.nj - half:, :] = s * I[f][:, :half, :][:, ::-1, :]
+    O.apply_bc(P, q)
+    return q
+
+
+def test_y_mirror_symmetry_full_size(C):
+    """Full configuration (256^3, Ra 1e5, 200 steps, 3D split): a y-mirror-
+    symmetric start stays symmetric bit for bit."""
+    say("mirror 256^3 x200")
+    P, g, prm = problem(C, (256, 256, 256), Ra=1e5)
+    cav = C.Cavity(g, prm, C.Halo((2, 2, 2), (1, 2, 2, 2, 2)))
+    cav.q.copy_(dev(y_symmetric_state(P, 2)))
+    cav.step(200)
+    I = P.interior(host(cav.q, P.shape))
+    for f in range(5):
+        s = -1.0 if f == 2 else 1.0
+        assert np.array_equal(I[f], s * I[f][:, ::-1, :]), O.FIELDS[f]
+    assert all(math.isfinite(x) for x in cav.norms())
+
+
+def test_determinism_and_restart(C):
+    say("determinism")
+    P, g, prm = problem(C, (48, 40, 33), Ra=1e4)
+    h = C.Halo((2, 2, 3), (1, 2, 2, 2, 2))
+    a = C.Cavity(g, prm, h).init(9)
+    b = C.Cavity(g, prm, h).init(9)
+    a.step(40)
+    b.step(17).step(23)
+    assert np.array_equal(host(a.q, P.shape), host(b.q, P.shape))
+    assert a.norms() == b.norms()
+    c = C.Cavity(g, prm, h).init(9)
+    c.step(40)
+    assert np.array_equal(P.interior(host(a.q, P.shape)), P.interior(host(c.q, P.shape)))
+
+
+def test_poisoned_scratch_is_overwritten(C):
+    """Every interior cell of the new state is written by the sweep."""
+    say("poison")
+    P, g, prm = problem(C, (70, 20, 11), Ra=1e3)
+    cav = C.Cavity(g, prm).init(4)
+    cav.q_tmp.fill_(float("nan"))
+    cav.step(1)
+    I = P.interior(host(cav.q, P.shape))
+    assert np.all(np.isfinite(I))
+
+
+def test_divergence_reports_nonfinite_norm(C):
+    say("divergence")
+    P, g, prm = problem(C, (8, 8, 8), Ra=1e3, cfl=50.0)
+    cav = C.Cavity(g, prm).init(1)
+    cav.step(80)
+    with pytest.raises(C.CavError) as e:
+        cav.norms()
+    assert e.value.code == C.CAV_ENONFINITE
