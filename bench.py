@@ -1,0 +1,226 @@
+"""Benchmark: pseudo-time steps of the 256^3 FP64 cavity on one MI355X.
+
+One step = wall ghost fill + halo pack + halo unpack of the 3D (2,2,2)
+virtual split + residual/update sweep with the centre rescale (the residual
+norms are reduced on the last step), i.e. one GPU's share of an iteration
+of the paper's solver (Xue & Roy, arXiv:2006.02602, Sec. 3.1 and 4.5).
+Inputs are seeded synthetic fields already resident in HBM.  Prints ONE JSON
+line; `value` is interior grid-point updates per second.
+
+    python bench.py [--gpus 1] [--steps 200] [--warmup 20] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
+SWEEP_BYTES_PER_CELL = 80      # read 5 + write 5 FP64 fields per interior cell
+PAPER_SSSPNT_P100 = 93.8       # single-GPU row of Tables 3-4 (P100, 256^3, no halo)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sweep_source_hash():
+    h = hashlib.sha256()
+    for f in ("sweep.hip", "cavity_internal.h"):
+        with open(os.path.join(ROOT, "paper_2006_02602_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel_hash):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter
+    summary, if it was taken on the current sweep source; else None."""
+    path = os.path.join(ROOT, "profiles", "sweep_cavity256_f64_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"sweep source hash:\s*`?([0-9a-f]+)", text)
+    m_bytes = re.search(r"calibrated HBM bytes per sweep launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash:
+        return None
+    return float(m_bytes.group(1))
+
+
+def halo_bench(C, torch, grid, cav, splits, widths_list, reps):
+    """Warm and cold (after a 1 GiB flush write) pack/unpack timings."""
+    out = []
+    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    for split in splits:
+        for widths in widths_list:
+            h = C.Halo(split, widths)
+            nbytes = C.halo_buffer_bytes(grid, h)
+            buf = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+            elems = nbytes // 8
+            res = {"split": list(split), "widths": list(widths), "values": elems}
+            for mode in ("warm", "cold"):
+                C.cavity_timing_read()
+                torch.cuda.synchronize()
+                for _ in range(reps):
+                    if mode == "cold":
+                        flush.zero_()
+                    C.cavity_timing_enable(True)
+                    C.halo_pack(grid, h, cav.q, buf)
+                    C.halo_unpack(grid, h, buf, cav.q)
+                    C.cavity_timing_enable(False)
+                torch.cuda.synchronize()
+                kt = C.cavity_timing_read()
+                for k in ("halo_pack", "halo_unpack"):
+                    n, ms = kt[k]
+                    us = 1e3 * ms / n
+                    res["%s_%s_us" % (k.split("_")[1], mode)] = round(us, 2)
+                    res["%s_%s_GBs" % (k.split("_")[1], mode)] = round(16.0 * elems / (us * 1e-6) / 1e9, 1)
+            out.append(res)
+            del buf
+    del flush
+    return out
+
+
+def cpu_baseline(wl, budget_s):
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    workload (same grid, parameters and halo; fewer steps)."""
+    import oracle as O
+    P = O.Problem(wl.n, Ra=wl.Ra, Pr=0.71, cfl=0.5)
+    q = O.init(P, wl.seed, wl.noise)
+    halo = (wl.splits[0], wl.widths)
+    t0 = time.perf_counter()
+    O.step(P, q, 1, halo=halo)
+    t1 = time.perf_counter() - t0
+    steps = max(1, min(40, int(round(budget_s / max(t1, 1e-3)))))
+    t0 = time.perf_counter()
+    O.step(P, q, steps, halo=halo)
+    dt = time.perf_counter() - t0
+    return {"value": P.ncell * steps / dt, "unit": "grid-point updates/s", "cores": O.threads(),
+            "kind": "oracle",
+            "sample": "%d^3 Ra %g, %d steps (of %d) with the %s split, whole step timed (%.1f s)"
+                      % (wl.n, wl.Ra, steps, wl.steps, "x".join(map(str, wl.splits[0])), dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="cavity256_f64_ra1e5")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--no-halo-bench", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU's share of the cavity; it does not run on %d GPUs "
+              "(there is no multi-GPU path in this library)" % max(args.gpus, int(os.environ.get("WORLD_SIZE", "1"))),
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2006_02602_amd as C
+    from paper_2006_02602_amd.configs import WORKLOADS
+
+    wl = WORKLOADS[args.workload]
+    K = args.steps if args.steps is not None else wl.steps
+    W = args.warmup
+    torch.cuda.set_device(0)
+    grid, prm, halo = wl.grid, wl.params, wl.halo()
+    log("bench: %s, %d warmup + %d timed steps, halo %s widths %s" % (wl.name, W, K, halo.split, halo.width))
+    cav = C.Cavity(grid, prm, halo).init(wl.seed, wl.noise)
+    torch.cuda.synchronize()
+
+    if args.calib_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    if W:
+        cav.step(W)
+    torch.cuda.synchronize()
+
+    # timed region: K whole steps
+    t0 = time.perf_counter()
+    cav.step(K)
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t0
+    norms = cav.norms()
+    log("bench: %.3f ms/step, norms %s" % (1e3 * t_run / K, norms))
+
+    # the same K steps again with HIP events around every launch, on the
+    # stream each kernel is launched on
+    C.cavity_timing_read()
+    C.cavity_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cav.step(K)
+    torch.cuda.synchronize()
+    t_ev = time.perf_counter() - t0
+    C.cavity_timing_enable(False)
+    kt = C.cavity_timing_read()
+    sw_n = sum(kt[k][0] for k in ("sweep", "sweep_norm") if k in kt)
+    sw_ms = sum(kt[k][1] for k in ("sweep", "sweep_norm") if k in kt) / sw_n
+    ncell = grid.ncell
+    achieved = SWEEP_BYTES_PER_CELL * ncell / (sw_ms * 1e-3) / 1e9
+    kh = sweep_source_hash()
+    traffic = counter_traffic(kh)
+    breakdown = {k: {"launches": n, "avg_us": round(1e3 * ms / n, 2)} for k, (n, ms) in sorted(kt.items())}
+    log("bench: sweep %.1f us -> %.0f GB/s algorithmic" % (1e3 * sw_ms, achieved))
+
+    halo_res = None
+    if not args.no_halo_bench:
+        splits = wl.splits
+        from paper_2006_02602_amd.configs import CONFIG_WIDTHS, PAPER_WIDTHS
+        halo_res = halo_bench(C, torch, grid, cav, splits, (CONFIG_WIDTHS, PAPER_WIDTHS), reps=10)
+        for r in halo_res:
+            log("bench: halo", r)
+
+    value = ncell * K / t_run
+    line = {
+        "metric": "grid-point updates/s + % HBM peak (stencil, pack/unpack); FP32 & batched vs FP64",
+        "value": value,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * t_run / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded SplitMix64 noise on rest state, T linear in x)",
+        "config": {"workload": "%s_split%s" % (wl.name, "x".join(map(str, halo.split))), "n": wl.n,
+                   "Ra": wl.Ra, "Pr": 0.71, "cfl": 0.5, "halo_split": list(halo.split),
+                   "halo_widths_p_u_v_w_T": list(halo.width), "parallelism": "single GPU"},
+        "ssspnt": value * 1e-7,
+        "paper_context": {"ssspnt_single_p100_256cubed": PAPER_SSSPNT_P100,
+                          "note": "P100, OpenACC Fortran, no halo in that row; context only"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "sweep_kernel", "bytes_per_launch": SWEEP_BYTES_PER_CELL * ncell,
+                     "avg_launch_us": 1e3 * sw_ms, "sweep_source_hash": kh},
+        "breakdown_us_per_launch": breakdown,
+        "ms_per_step_with_events": 1e3 * t_ev / K,
+        "residual_norms": norms,
+    }
+    if halo_res is not None:
+        line["halo"] = halo_res
+    if not args.no_cpu:
+        log("bench: CPU baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+        log("bench: CPU baseline", line["cpu_baseline"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
