@@ -19,8 +19,10 @@
  *         q[((f*(nk+2g) + (k+g))*(nj+2g) + (j+g))*(ni+2g) + (i+g)]
  *     with g = ng = 2 ghost layers per side (Listing 1: "interior cell index
  *     starts at 3"), i fastest and k slowest (Sec. 3.1), (i,j,k) = (x,y,z).
- *     Interior cells are 0 <= i < ni etc.  Edge and corner ghost cells are
- *     never read or written.  Element type: double when dtype == CAV_F64.
+ *     Interior cells are 0 <= i < ni etc.  cavity_init also fills the face
+ *     ghost layers; cavity_step never reads a ghost cell (their contents
+ *     after a step are unspecified).
+ *     Element type: double when dtype == CAV_F64.
  *   - Pointers are DEVICE pointers unless the comment says (host).  The
  *     caller owns every buffer; the library allocates no device memory and
  *     keeps no pointer after a call returns.
@@ -108,25 +110,27 @@ size_t halo_buffer_bytes(const cav_grid* grid, const cav_halo* halo);
  * where idx = i + ni*(j + nj*k) and noise(seed, f, idx) = (2r - 1)*noise_amp
  * with r = (z >> 11) * 2^-53, z the output number f*2^40 + idx (0-based) of
  * the SplitMix64 generator seeded with `seed` (Steele, Lea & Flood, 2014).
- * Then the wall ghost layers are filled as cavity_step does.
+ * Then the face ghost layers are filled with the wall rules of cavity_step.
  * q: device, cavity_state_elems(grid) elements, written. */
 int cavity_init(const cav_grid* grid, const cav_params* prm, uint64_t seed,
                 double noise_amp, void* q, hipStream_t stream);
 
 /* Advance the state `nsteps` >= 0 pseudo-time steps (Sec. 2; Sec. 3.1).
  * Each step, in this order:
- *   1. fill the wall ghost layers of q (Sec. 2: no-slip velocity; T fixed
- *      on the hot/cold walls and zero-gradient on the adiabatic walls,
- *      second order; p extrapolated linearly, one-sided second order),
- *   2. if halo != NULL: halo_pack into halo_buf, then halo_unpack from it
+ *   1. if halo != NULL: halo_pack into halo_buf, then halo_unpack from it
  *      (all virtual subdomains live in q, so the exchange is a round trip),
- *   3. for every interior cell: residuals R_p, R_u, R_v, R_w, R_T of
+ *   2. for every interior cell: residuals R_p, R_u, R_v, R_w, R_T of
  *      Eq. 1-3 (second-order central differences; fourth-difference
  *      pressure dissipation), local time step, q' = q + dt*R written to
- *      q_tmp (Jacobi: every residual uses the old state),
- *   4. p' -= p'(ni/2, nj/2, nk/2) over the interior (Sec. 2, rescale at the
+ *      q_tmp (Jacobi: every residual uses the old state).  The wall ghost
+ *      values the stencils reach (Sec. 2: no-slip velocity; T fixed on the
+ *      hot/cold walls and zero-gradient on the adiabatic walls, second
+ *      order; p extrapolated linearly, one-sided second order) are derived
+ *      from interior cells as they are loaded: no ghost cell of q or q_tmp
+ *      is read,
+ *   3. p' -= p'(ni/2, nj/2, nk/2) over the interior (Sec. 2, rescale at the
  *      centre point every iteration),
- *   5. swap q and q_tmp.
+ *   4. swap q and q_tmp.
  * On return the newest state is in q (for odd nsteps the library copies it
  * back from q_tmp); q_tmp holds scratch.  The residual L2 norms of the last
  * step are left in ws for cavity_residual_norm.

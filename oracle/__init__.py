@@ -53,6 +53,8 @@ def lib():
         L.orc_halo_pack.argtypes = [pp, hp, dp, dp]
         L.orc_halo_unpack.argtypes = [pp, hp, dp, dp]
         L.orc_step.argtypes = [pp, hp, dp, dp, dp, ctypes.c_int, dp]
+        L.orc_nusselt_hot.restype = ctypes.c_double
+        L.orc_nusselt_hot.argtypes = [pp, dp]
         L.orc_splitmix64.restype = ctypes.c_uint64
         L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         L.orc_threads.restype = ctypes.c_int
@@ -162,6 +164,12 @@ def step(P: Problem, q: np.ndarray, nsteps: int, halo=None):
     lib().orc_step(ctypes.byref(c), ctypes.byref(h) if h is not None else None, _dp(q), _dp(tmp),
                    _dp(buf), int(nsteps), _dp(norms))
     return norms
+
+
+def nusselt_hot(P: Problem, q: np.ndarray) -> float:
+    """Mean Nusselt number of the hot wall (x = 0) of state q, FP64."""
+    c = P._c()
+    return float(lib().orc_nusselt_hot(ctypes.byref(c), _dp(q)))
 
 
 def splitmix64(seed: int, n: int) -> int:

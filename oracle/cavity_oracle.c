@@ -359,6 +359,32 @@ void orc_halo_unpack(const orc_problem* P, const orc_halo* H, const double* buf,
 }
 
 /* ------------------------------------------------------------------ */
+/* Mean Nusselt number of the hot wall x = 0 (Reading: the paper's cavity
+ * transfers heat between its vertical walls, Sec. 2; the nondimensional
+ * wall heat flux is -dT/dx, and the temperature scale is t_hot - t_cold).
+ * dT/dx at the wall from the second-order one-sided difference through the
+ * wall value T_w and the first two cell centres (x = h/2, 3h/2):
+ *   dT/dx = (9 T_0 - T_1 - 8 T_w) / (3 h)
+ * Nu = mean over (j, k) of -dT/dx / (t_hot - t_cold).  FP64 sums over k
+ * planes in order. */
+double orc_nusselt_hot(const orc_problem* P, const double* q)
+{
+    const double h = 1.0 / (double)P->ni;
+    double total = 0.0;
+    for (int k = 0; k < P->nk; ++k) {
+        double plane = 0.0;
+        for (int j = 0; j < P->nj; ++j) {
+            const double tw = P->t_hot_field ? P->t_hot_field[j + (size_t)P->nj * k] : P->t_hot;
+            const double t0 = q[at(P, FT, 0, j, k)], t1 = q[at(P, FT, 1, j, k)];
+            const double dtdx = (9.0 * t0 - t1 - 8.0 * tw) / (3.0 * h);
+            plane += -dtdx;
+        }
+        total += plane;
+    }
+    return total / ((double)P->nj * (double)P->nk) / (P->t_hot - P->t_cold);
+}
+
+/* ------------------------------------------------------------------ */
 /* Pseudo-time stepping (Sec. 2; Sec. 3.1: a loop over all nodes inside the
  * pseudo-time loop).  Per step: wall ghosts, optional halo round trip,
  * residual + Euler update of every interior cell into q_tmp (Jacobi),

@@ -43,6 +43,7 @@ void   orc_halo_pack(const orc_problem* P, const orc_halo* H, const double* q, d
 void   orc_halo_unpack(const orc_problem* P, const orc_halo* H, const double* buf, double* q);
 void   orc_step(const orc_problem* P, const orc_halo* H, double* q, double* q_tmp,
                 double* buf, int nsteps, double* norms);
+double orc_nusselt_hot(const orc_problem* P, const double* q);
 uint64_t orc_splitmix64(uint64_t seed, uint64_t n);
 int    orc_threads(void);
 

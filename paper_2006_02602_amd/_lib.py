@@ -7,7 +7,8 @@ import ctypes
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libcavity.so")
+# CAVITY_LIB selects another build of the same library (e.g. for A/B timing)
+LIB_PATH = os.environ.get("CAVITY_LIB") or os.path.join(PKG, "libcavity.so")
 
 CAV_OK = 0
 CAV_EINVAL = -1

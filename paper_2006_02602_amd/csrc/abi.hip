@@ -145,6 +145,8 @@ Coef coef_of(const cav_grid* g, const cav_params* p)
     c.cfl = p->cfl;
     const double dmax = c.nu > c.alpha ? c.nu : c.alpha;
     c.dt_visc = 1.0 / (2.0 * dmax * (nx * nx + ny * ny + nz * nz));
+    c.t_hot = p->t_hot;
+    c.t_cold = p->t_cold;
     return c;
 }
 
@@ -275,16 +277,13 @@ int cavity_step(const cav_grid* grid, const cav_params* prm, const cav_halo* hal
 
     const Coef c = coef_of(grid, prm);
     const SweepGeom g = sweep_geom(d);
-    const Bcs bc{prm->t_hot, prm->t_cold};
     double* wsd = static_cast<double*>(ws);
     double* partials = reinterpret_cast<double*>(static_cast<char*>(ws) + WS_HEAD);
     void* cur = q;
     void* nxt = q_tmp;
     hipError_t e;
     for (int n = 0; n < nsteps; ++n) {
-        const State sc = state_of(cur, d);
-        e = run("bc", stream, [&] { return launch_bc(d, bc, sc, stream); });
-        if (e != hipSuccess) return hip_fail("bc launch", e);
+        // the wall ghosts are derived inside the sweep; no separate pass
         if (halo) {
             if ((rc = do_halo(grid, hg, cur, halo_buf, true, stream))) return rc;
             if ((rc = do_halo(grid, hg, cur, halo_buf, false, stream))) return rc;

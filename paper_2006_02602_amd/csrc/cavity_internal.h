@@ -43,6 +43,7 @@ struct Coef {
     double t_inf;             // buoyancy reference temperature
     double cfl;
     double dt_visc;           // 1 / (2 max(nu, alpha) (nx^2 + ny^2 + nz^2))
+    double t_hot, t_cold;     // hot (x = 0) and cold (x = 1) wall temperatures
 };
 
 // Sweep launch geometry.

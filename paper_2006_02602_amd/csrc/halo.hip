@@ -57,41 +57,62 @@ __global__ __launch_bounds__(256) void halo_kernel(Dims d, HaloGeom h, State q, 
         const bool hi2 = f2 & 1;
         if (!(hi2 ? cc[ax2] == h.P[ax2] - 1 : cc[ax2] == 0)) u += h.area[ax2];
     }
-    double* B = buf + u * h.wsum;
+    double* __restrict__ B = buf + u * h.wsum;
 
+    // this thread's tangential cell, the first layer's offset per field and
+    // the stride between layers (all fields first, then all stores, so that
+    // every load is in flight before the first store)
     const int ex = h.e[0], ey = h.e[1], ez = h.e[2];
+    int ta, tb;                       // tangential coordinates
+    long long lay_b;                  // buffer stride between layers
+    int lay_q;                        // state stride between layers
+    if (axis == 0) { ta = t % ey; tb = t / ey; lay_b = 1; lay_q = 1; }
+    else if (axis == 1) { ta = t % ex; tb = t / ex; lay_b = ex; lay_q = d.sy; }
+    else { ta = t % ex; tb = t / ex; lay_b = (long long)ex * ey; lay_q = d.sz; }
+    int qo[NF];
+    long long bo[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         const int w = h.w[f];
-        if (w == 0) continue;
-        double* Bf = B + (long long)h.wpre[f] * area;
-        double* Q = q.f[f];
+        const long long base = (long long)h.wpre[f] * area;
         if (axis == 0) {
-            const int jj = t % ey, kk = t / ey;
             const int gi = high ? (a + 1) * ex - w : a * ex;
-            const int o = cell_off(d, gi, b * ey + jj, c * ez + kk);
-            for (int l = 0; l < w; ++l) {
-                if (PACK) Bf[(long long)t * w + l] = Q[o + l];
-                else      Q[o + l] = Bf[(long long)t * w + l];
-            }
+            qo[f] = cell_off(d, gi, b * ey + ta, c * ez + tb);
+            bo[f] = base + (long long)t * w;
         } else if (axis == 1) {
-            const int ii = t % ex, kk = t / ex;
             const int gj = high ? (b + 1) * ey - w : b * ey;
-            const int o = cell_off(d, a * ex + ii, gj, c * ez + kk);
-            for (int l = 0; l < w; ++l) {
-                const long long x = ((long long)kk * w + l) * ex + ii;
-                if (PACK) Bf[x] = Q[o + l * d.sy];
-                else      Q[o + l * d.sy] = Bf[x];
-            }
+            qo[f] = cell_off(d, a * ex + ta, gj, c * ez + tb);
+            bo[f] = base + (long long)tb * w * ex + ta;
         } else {
-            const int ii = t % ex, jj = t / ex;
             const int gk = high ? (c + 1) * ez - w : c * ez;
-            const int o = cell_off(d, a * ex + ii, b * ey + jj, gk);
-            for (int l = 0; l < w; ++l) {
-                const long long x = ((long long)l * ey + jj) * ex + ii;
-                if (PACK) Bf[x] = Q[o + l * d.sz];
-                else      Q[o + l * d.sz] = Bf[x];
-            }
+            qo[f] = cell_off(d, a * ex + ta, b * ey + tb, gk);
+            bo[f] = base + (long long)tb * ex + ta;
+        }
+    }
+    double v0[NF], v1[NF];
+    if (PACK) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const double* __restrict__ Q = q.f[f];
+            if (h.w[f] > 0) v0[f] = Q[qo[f]];
+            if (h.w[f] > 1) v1[f] = Q[qo[f] + lay_q];
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (h.w[f] > 0) B[bo[f]] = v0[f];
+            if (h.w[f] > 1) B[bo[f] + lay_b] = v1[f];
+        }
+    } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (h.w[f] > 0) v0[f] = B[bo[f]];
+            if (h.w[f] > 1) v1[f] = B[bo[f] + lay_b];
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            double* __restrict__ Q = q.f[f];
+            if (h.w[f] > 0) Q[qo[f]] = v0[f];
+            if (h.w[f] > 1) Q[qo[f] + lay_q] = v1[f];
         }
     }
 }

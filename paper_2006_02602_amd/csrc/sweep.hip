@@ -5,7 +5,8 @@
 // Boussinesq equations (Sec. 2, Eq. 1-3), second-order central differences
 // with a fourth-difference pressure dissipation (5-point p stencil, 3-point
 // stencils for u, v, w, T; Sec. 3.1), first-order explicit Euler in pseudo
-// time, pressure rescaled at the cavity centre every iteration (Sec. 2).
+// time, wall boundary conditions and the pressure rescale at the cavity
+// centre in every iteration (Sec. 2).
 //
 // This file is compiled with -ffp-contract=off: every fused multiply-add is
 // written out with fma(), so two inlined copies of the per-cell update round
@@ -35,6 +36,32 @@ __device__ __forceinline__ double lap3(const Coef& c, double q, double xm, doubl
     return fma(c.ix2, fma(-2.0, q, xp + xm), fma(c.iy2, fma(-2.0, q, yp + ym), c.iz2 * fma(-2.0, q, zp + zm)));
 }
 
+// Square root of a positive argument: hardware reciprocal-square-root
+// estimate refined by Goldschmidt's iteration (one coupled step for
+// sqrt(x) and 1/(2 sqrt(x)), then a final residual correction), within an
+// ulp of the correctly rounded result.  Arguments below 1e-300 are clamped.
+__device__ __forceinline__ double sqrt_pos(double x)
+{
+    x = fmax(x, 1e-300);
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    return fma(h, d, g);
+}
+
+// 1/x for x > 0: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double recip_pos(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
 __device__ __forceinline__ void cell_residual(const Coef& c, const Star& s, double R[NF], double& dt)
 {
     // first differences (times 2h)
@@ -51,10 +78,10 @@ __device__ __forceinline__ void cell_residual(const Coef& c, const Star& s, doub
     const double u2 = s.u * s.u, v2 = s.v * s.v, w2 = s.w * s.w;
     const double beta2 = fmax((u2 + v2) + w2, c.beta2_floor);
     const double b4 = 4.0 * beta2;
-    const double lxn = (fabs(s.u) + sqrt(u2 + b4)) * c.hx2;   // lambda_x / h_x
-    const double lyn = (fabs(s.v) + sqrt(v2 + b4)) * c.hy2;
-    const double lzn = (fabs(s.w) + sqrt(w2 + b4)) * c.hz2;
-    dt = c.cfl * fmin(1.0 / ((lxn + lyn) + lzn), c.dt_visc);
+    const double lxn = (fabs(s.u) + sqrt_pos(u2 + b4)) * c.hx2;   // lambda_x / h_x
+    const double lyn = (fabs(s.v) + sqrt_pos(v2 + b4)) * c.hy2;
+    const double lzn = (fabs(s.w) + sqrt_pos(w2 + b4)) * c.hz2;
+    dt = c.cfl * fmin(recip_pos((lxn + lyn) + lzn), c.dt_visc);
 
     // continuity (Eq. 1 times beta^2) with fourth-difference dissipation
     const double div = fma(dxu, c.hx2, fma(dyv, c.hy2, dzw * c.hz2));
@@ -76,24 +103,105 @@ __device__ __forceinline__ void cell_residual(const Coef& c, const Star& s, doub
     R[FT] = fma(c.alpha, lap3(c, s.t, s.txm, s.txp, s.tym, s.typ, s.tzm, s.tzp), -adt);
 }
 
-// Gather the stars of one cell straight from global memory (used once per
-// block for the centre cell).
-__device__ __forceinline__ void gather_global(const Dims& d, const CState& q, int i, int j, int k, Star& s)
+// ---------------------------------------------------------------------------
+// Wall ghosts on the fly (Sec. 2).  The state in HBM holds only interior
+// cells that the sweep reads; a face-ghost value g = 1, 2 layers beyond a
+// wall is derived from the interior cells m0 (next to the wall) and m1:
+//   p:        g1 = 2 q(m0) - q(m1), g2 = 2 g1 - q(m0)  (one-sided linear
+//             extrapolation, second order)
+//   u, v, w:  g = -q(m_{g-1})                          (no-slip)
+//   T:        g = 2 T_wall - q(m_{g-1}) on the hot (x = 0) and cold (x = 1)
+//             walls, g = q(m_{g-1}) on the adiabatic walls.
+enum { SIDE_X_LO = 0, SIDE_X_HI = 1, SIDE_OTHER = 2 };
+constexpr int SLOT_UNUSED = 3;
+
+// Where a thread reads one (i, j) column of every plane: the cell itself
+// (code 0), or the two mirror cells of a face ghost (code = g | side << 2),
+// or nothing (edge/corner column or beyond the ghosts: code 3).
+struct Slot {
+    int oa, ob, code;
+};
+
+__device__ __forceinline__ Slot make_slot(const Dims& d, int i, int j)
 {
-    const int o = cell_off(d, i, j, k);
-    const int X = 1, Y = d.sy, Z = d.sz;
-    const double* P = q.f[FP];
-    s.p = P[o];
-    s.pxm = P[o - X]; s.pxp = P[o + X]; s.pxm2 = P[o - 2 * X]; s.pxp2 = P[o + 2 * X];
-    s.pym = P[o - Y]; s.pyp = P[o + Y]; s.pym2 = P[o - 2 * Y]; s.pyp2 = P[o + 2 * Y];
-    s.pzm = P[o - Z]; s.pzp = P[o + Z]; s.pzm2 = P[o - 2 * Z]; s.pzp2 = P[o + 2 * Z];
-#define STAR7(F, nm)                                                              \
-    {                                                                             \
-        const double* A = q.f[F];                                                 \
-        s.nm = A[o];                                                              \
-        s.nm##xm = A[o - X]; s.nm##xp = A[o + X];                                 \
-        s.nm##ym = A[o - Y]; s.nm##yp = A[o + Y];                                 \
-        s.nm##zm = A[o - Z]; s.nm##zp = A[o + Z];                                 \
+    Slot s{0, 0, SLOT_UNUSED};
+    const bool ii = i >= 0 && i < d.ni, jj = j >= 0 && j < d.nj;
+    if (ii && jj) {
+        s.oa = cell_off(d, i, j, 0);
+        s.code = 0;
+    } else if (!ii && jj) {
+        const bool lo = i < 0;
+        const int g = lo ? -i : i - d.ni + 1;
+        if (g <= NG) {
+            s.oa = cell_off(d, lo ? 0 : d.ni - 1, j, 0);
+            s.ob = cell_off(d, lo ? 1 : d.ni - 2, j, 0);
+            s.code = g | ((lo ? SIDE_X_LO : SIDE_X_HI) << 2);
+        }
+    } else if (ii && !jj) {
+        const bool lo = j < 0;
+        const int g = lo ? -j : j - d.nj + 1;
+        if (g <= NG) {
+            s.oa = cell_off(d, i, lo ? 0 : d.nj - 1, 0);
+            s.ob = cell_off(d, i, lo ? 1 : d.nj - 2, 0);
+            s.code = g | (SIDE_OTHER << 2);
+        }
+    }
+    return s;
+}
+
+__device__ __forceinline__ double ghost_value(int f, int code, double a, double b, const Coef& c)
+{
+    const int g = code & 3, side = code >> 2;
+    if (f == FP) {
+        const double g1 = 2.0 * a - b;
+        return g == 1 ? g1 : 2.0 * g1 - a;
+    }
+    const double m = g == 1 ? a : b;
+    if (f == FT) return side == SIDE_X_LO ? 2.0 * c.t_hot - m : (side == SIDE_X_HI ? 2.0 * c.t_cold - m : m);
+    return -m;
+}
+
+__device__ __forceinline__ double slot_load(const double* G, const Slot& s, int kz, int f, const Coef& c)
+{
+    double v = 0.0;
+    if (s.code == 0)
+        v = G[s.oa + kz];
+    else if (s.code != SLOT_UNUSED)
+        v = ghost_value(f, s.code, G[s.oa + kz], G[s.ob + kz], c);
+    return v;
+}
+
+// Any interior or face-ghost value, straight from global memory (used once
+// per block, for the stars of the centre cell).
+__device__ __forceinline__ double value_at(const Dims& d, const CState& q, const Coef& c, int f, int i, int j,
+                                           int k)
+{
+    const double* G = q.f[f];
+    if (k < 0 || k >= d.nk) {
+        const bool lo = k < 0;
+        const int g = lo ? -k : k - d.nk + 1;
+        const double a = G[cell_off(d, i, j, lo ? 0 : d.nk - 1)];
+        const double b = G[cell_off(d, i, j, lo ? 1 : d.nk - 2)];
+        return ghost_value(f, g | (SIDE_OTHER << 2), a, b, c);
+    }
+    return slot_load(G, make_slot(d, i, j), k * d.sz, f, c);
+}
+
+__device__ __forceinline__ void gather_global(const Dims& d, const CState& q, const Coef& c, int i, int j, int k,
+                                              Star& s)
+{
+    auto P = [&](int di, int dj, int dk) { return value_at(d, q, c, FP, i + di, j + dj, k + dk); };
+    s.p = P(0, 0, 0);
+    s.pxm = P(-1, 0, 0); s.pxp = P(1, 0, 0); s.pxm2 = P(-2, 0, 0); s.pxp2 = P(2, 0, 0);
+    s.pym = P(0, -1, 0); s.pyp = P(0, 1, 0); s.pym2 = P(0, -2, 0); s.pyp2 = P(0, 2, 0);
+    s.pzm = P(0, 0, -1); s.pzp = P(0, 0, 1); s.pzm2 = P(0, 0, -2); s.pzp2 = P(0, 0, 2);
+#define STAR7(F, nm)                                                                  \
+    {                                                                                 \
+        auto A = [&](int di, int dj, int dk) { return value_at(d, q, c, F, i + di, j + dj, k + dk); }; \
+        s.nm = A(0, 0, 0);                                                            \
+        s.nm##xm = A(-1, 0, 0); s.nm##xp = A(1, 0, 0);                                \
+        s.nm##ym = A(0, -1, 0); s.nm##yp = A(0, 1, 0);                                \
+        s.nm##zm = A(0, 0, -1); s.nm##zp = A(0, 0, 1);                                \
     }
     STAR7(FU, u) STAR7(FV, v) STAR7(FW, w) STAR7(FT, t)
 #undef STAR7
@@ -111,11 +219,13 @@ __device__ __forceinline__ int xcd_block(int bid, int nb)
 
 // ---------------------------------------------------------------------------
 // The sweep.  Block = one 64 x 8 tile of (i, j) columns (one wavefront per
-// j row, i along the lanes) marching over a chunk of k planes.  The current
-// plane k of all five fields lives in LDS with its i/j halo (2 for p, 1 for
-// the rest); the k neighbours come from per-thread register queues (p:
-// k-2..k+2, others k-1..k+1).  While plane k is computed, the loads of
-// plane k+1's halo strips and of the next queue entries are in flight.
+// j row, i along the lanes) marching over a chunk of k planes.  Plane k of
+// all five fields lives in LDS with its i/j halo (2 for p, 1 for the rest);
+// the k neighbours come from per-thread register queues (p: k-2..k+2,
+// others k-1..k+1).  The LDS planes are double-buffered: plane k+1 is
+// written into one buffer while plane k is computed from the other, so each
+// plane costs one barrier; global loads run two planes ahead.
+// Wall ghosts are derived while loading (Slot), never read from HBM.
 template <bool NORM>
 __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef c, SweepGeom g, CState q,
                                                               State qn, double* partials)
@@ -123,9 +233,10 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef c, Sw
     constexpr int TI = SW_TI, TJ = SW_TJ;
     constexpr int PW = TI + 4;              // LDS row pitch, p
     constexpr int UW = TI + 2;              // LDS row pitch, u v w T
+    constexpr int PPL = (TJ + 4) * PW;      // LDS plane, p
     constexpr int UPL = (TJ + 2) * UW;      // LDS plane, one of u v w T
-    __shared__ double sP[(TJ + 4) * PW];
-    __shared__ double sU[4 * UPL];
+    __shared__ double sP[2 * PPL];
+    __shared__ double sU[2 * 4 * UPL];
 
     const int b = xcd_block(blockIdx.x, g.nblocks);
     const int bi = b % g.tiles_i;
@@ -138,124 +249,207 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef c, Sw
     const int lane = threadIdx.x, row = threadIdx.y;
     const int i = i0 + lane, j = j0 + row;
     const bool active = i < d.ni && j < d.nj;
-    const bool present = i < d.ni + NG && j < d.nj + NG;   // cell exists in memory
 
     // New pressure at the centre cell, recomputed with the same arithmetic
     // as its owner, so that every block subtracts the identical value.
     double pc_new;
     {
         Star s;
-        gather_global(d, q, d.ni / 2, d.nj / 2, d.nk / 2, s);
+        gather_global(d, q, c, d.ni / 2, d.nj / 2, d.nk / 2, s);
         double R[NF], dt;
         cell_residual(c, s, R, dt);
         pc_new = fma(dt, R[FP], s.p);
     }
 
-    // ---- strip assignments (fixed for the whole march) ----
-    // p rows j0-2, j0-1, j0+TJ, j0+TJ+1: waves 0..3, one row each.
-    const int prow_lds = row < 2 ? row : TJ + row;               // LDS row (p)
+    // ---- what this thread loads (fixed for the whole march) ----
+    // Only interior cells are loaded.  LDS cells that hold wall ghosts are
+    // filled from interior LDS cells (fix_ghosts), the k neighbours beyond
+    // the z walls by recurrences on the register queues.
+    auto interior = [&](int ii, int jj) { return ii >= 0 && ii < d.ni && jj >= 0 && jj < d.nj; };
+    // p rows j0-2, j0-1, j0+TJ, j0+TJ+1: waves 0..3, one row each
+    const bool has_prow = row < 4;
+    const int prow_lds = row < 2 ? row : TJ + row;
     const int prow_j = j0 - 2 + prow_lds;
-    const bool has_prow = row < 4 && i < d.ni + NG && prow_j < d.nj + NG;
-    // u v w T rows j0-1, j0+TJ: waves 0..7, field 1 + row/2.
-    const int urow_f = row >> 1;                                  // 0..3 -> u v w T
+    const bool ld_prow = has_prow && interior(i, prow_j);
+    // u v w T rows j0-1, j0+TJ: waves 0..7, field 1 + row/2
+    const int urow_f = FU + (row >> 1);
     const int urow_lds = (row & 1) ? TJ + 1 : 0;
     const int urow_j = j0 - 1 + urow_lds;
-    const bool has_urow = i < d.ni + NG && urow_j < d.nj + NG;
-    // column halos of this wave's row: lanes 0..3 p (i0-2, i0-1, i0+TI, i0+TI+1),
-    // lanes 4..11 u v w T (i0-1, i0+TI).
-    int col_i, col_f, col_lds;
+    const bool ld_urow = interior(i, urow_j);
+    // column halos of this wave's row: lanes 0..3 p (i0-2, i0-1, i0+TI,
+    // i0+TI+1), lanes 4..11 u v w T (i0-1, i0+TI)
+    const bool has_col = lane < 12;
+    int col_f, col_lds, col_i;
     if (lane < 4) {
         col_f = FP;
-        col_lds = lane < 2 ? lane : TI + lane;                   // LDS column (p)
-        col_i = i0 - 2 + col_lds;
-        col_lds += (row + 2) * PW;
+        const int cc = lane < 2 ? lane : TI + lane;
+        col_i = i0 - 2 + cc;
+        col_lds = (row + 2) * PW + cc;
     } else {
-        const int t = lane - 4;
-        col_f = min(FU + (t >> 1), (int)FT);
-        const int cc = (t & 1) ? TI + 1 : 0;                     // LDS column (u v w T)
+        const int t = min(lane - 4, 7);
+        col_f = FU + (t >> 1);
+        const int cc = (t & 1) ? TI + 1 : 0;
         col_i = i0 - 1 + cc;
         col_lds = (col_f - FU) * UPL + (row + 1) * UW + cc;
     }
-    const bool has_col = lane < 12 && col_i < d.ni + NG && j < d.nj + NG;
-
-    const int off_c = cell_off(d, i, j, 0);                      // this column at k = 0
+    const bool ld_col = has_col && interior(col_i, j);
+    const int prow_dst = prow_lds * PW + lane + 2;
+    const int urow_dst = (urow_f - FU) * UPL + urow_lds * UW + lane + 1;
+    const int off_c = cell_off(d, i, j, 0);
     const int off_prow = cell_off(d, i, prow_j, 0);
     const int off_urow = cell_off(d, i, urow_j, 0);
     const int off_col = cell_off(d, col_i, j, 0);
-    const double* Pg = q.f[FP];
-    const double* Ug = q.f[FU];
-    const double* Vg = q.f[FV];
-    const double* Wg = q.f[FW];
-    const double* Tg = q.f[FT];
-    const double* URg = q.f[FU + urow_f];
-    const double* COLg = q.f[col_f];
+    const double* const Pg = q.f[FP];
+    const double* const Ug = q.f[FU];
+    const double* const Vg = q.f[FV];
+    const double* const Wg = q.f[FW];
+    const double* const Tg = q.f[FT];
+    const double* const URg = q.f[urow_f];
+    const double* const COLg = q.f[col_f];
     const int Z = d.sz;
 
+    // tiles whose LDS planes reach past a wall fix their ghost cells
+    const bool bnd = i0 == 0 || j0 == 0 || i0 + TI + 2 > d.ni || j0 + TJ + 2 > d.nj;
+    auto fix_ghosts = [&](double* fP, double* fU) __attribute__((always_inline)) {
+        auto cell = [&](int f, int ci, int cj) -> double& {
+            return f == FP ? fP[(cj - j0 + 2) * PW + (ci - i0 + 2)]
+                           : fU[(f - FU) * UPL + (cj - j0 + 1) * UW + (ci - i0 + 1)];
+        };
+        // y walls: column i0 + lane, field `row`
+        if (row < NF && i < d.ni) {
+            const int f = row, reach = f == FP ? 2 : 1;
+            if (j0 == 0) {
+                const double a = cell(f, i, 0), b = cell(f, i, 1);
+                for (int gg = 1; gg <= reach; ++gg) cell(f, i, -gg) = ghost_value(f, gg | (SIDE_OTHER << 2), a, b, c);
+            }
+            if (j0 + TJ + reach > d.nj) {
+                const double a = cell(f, i, d.nj - 1), b = cell(f, i, d.nj - 2);
+                for (int gg = 1; gg <= reach; ++gg)
+                    if (d.nj - 1 + gg < j0 + TJ + reach)
+                        cell(f, i, d.nj - 1 + gg) = ghost_value(f, gg | (SIDE_OTHER << 2), a, b, c);
+            }
+        }
+        // x walls: row j0 + row, field `lane`
+        if (lane < NF && j < d.nj) {
+            const int f = lane, reach = f == FP ? 2 : 1;
+            if (i0 == 0) {
+                const double a = cell(f, 0, j), b = cell(f, 1, j);
+                for (int gg = 1; gg <= reach; ++gg) cell(f, -gg, j) = ghost_value(f, gg | (SIDE_X_LO << 2), a, b, c);
+            }
+            if (i0 + TI + reach > d.ni) {
+                const double a = cell(f, d.ni - 1, j), b = cell(f, d.ni - 2, j);
+                for (int gg = 1; gg <= reach; ++gg)
+                    if (d.ni - 1 + gg < i0 + TI + reach)
+                        cell(f, d.ni - 1 + gg, j) = ghost_value(f, gg | (SIDE_X_HI << 2), a, b, c);
+            }
+        }
+    };
+
     // ---- register queues ----
-    double p0 = 0, p1 = 0, p2 = 0, p3 = 0;          // p at k-2, k-1, k, k+1
-    double u0 = 0, u1 = 0, v0 = 0, v1 = 0, w0 = 0, w1 = 0, t0 = 0, t1 = 0;  // k-1, k
-    double np_ = 0, nu_ = 0, nv_ = 0, nw_ = 0, nt_ = 0;   // in flight: p(k+2), uvwT(k+1)
-    double r_prow = 0, r_urow = 0, r_col = 0;              // in flight: strips of plane k
-    if (present) {
-        p0 = Pg[off_c + (k0 - 2) * Z];
-        p1 = Pg[off_c + (k0 - 1) * Z];
-        p2 = Pg[off_c + k0 * Z];
-        p3 = Pg[off_c + (k0 + 1) * Z];
-        u0 = Ug[off_c + (k0 - 1) * Z]; u1 = Ug[off_c + k0 * Z];
-        v0 = Vg[off_c + (k0 - 1) * Z]; v1 = Vg[off_c + k0 * Z];
-        w0 = Wg[off_c + (k0 - 1) * Z]; w1 = Wg[off_c + k0 * Z];
-        t0 = Tg[off_c + (k0 - 1) * Z]; t1 = Tg[off_c + k0 * Z];
-        np_ = Pg[off_c + (k0 + 2) * Z];
-        nu_ = Ug[off_c + (k0 + 1) * Z];
-        nv_ = Vg[off_c + (k0 + 1) * Z];
-        nw_ = Wg[off_c + (k0 + 1) * Z];
-        nt_ = Tg[off_c + (k0 + 1) * Z];
+    double p0, p1, p2, p3;                                 // p at k-2, k-1, k, k+1
+    double u0, u1, v0, v1, w0, w1, t0, t1;                 // at k-1, k
+    const int lc_p = (row + 2) * PW + lane + 2;            // this cell in an LDS p plane
+    const int lc_u = (row + 1) * UW + lane + 1;            // this cell in an LDS u v w T plane
+    {
+        // planes k0-2 .. k0+1 of this column; planes beyond the z walls
+        // follow from the wall rules (recurrences along k)
+        double P[4], U[2], V[2], W[2], T[2];
+        for (int m = 0; m < 4; ++m) {
+            const int kk = k0 - 2 + m;
+            P[m] = (active && kk >= 0 && kk < d.nk) ? Pg[off_c + kk * Z] : 0.0;
+        }
+        for (int m = 0; m < 2; ++m) {
+            const int kk = k0 - 1 + m;
+            const bool in = active && kk >= 0;
+            U[m] = in ? Ug[off_c + kk * Z] : 0.0;
+            V[m] = in ? Vg[off_c + kk * Z] : 0.0;
+            W[m] = in ? Wg[off_c + kk * Z] : 0.0;
+            T[m] = in ? Tg[off_c + kk * Z] : 0.0;
+        }
+        if (k0 + 1 >= d.nk) P[3] = 2.0 * P[2] - P[1];
+        for (int m = 1; m >= 0; --m)
+            if (k0 - 2 + m < 0) P[m] = 2.0 * P[m + 1] - P[m + 2];
+        if (k0 - 1 < 0) { U[0] = -U[1]; V[0] = -V[1]; W[0] = -W[1]; T[0] = T[1]; }
+        p0 = P[0]; p1 = P[1]; p2 = P[2]; p3 = P[3];
+        u0 = U[0]; u1 = U[1]; v0 = V[0]; v1 = V[1]; w0 = W[0]; w1 = W[1]; t0 = T[0]; t1 = T[1];
     }
-    if (has_prow) r_prow = Pg[off_prow + k0 * Z];
-    if (has_urow) r_urow = URg[off_urow + k0 * Z];
-    if (has_col) r_col = COLg[off_col + k0 * Z];
+    // plane k0 into LDS buffer 0
+    sP[lc_p] = p2;
+    sU[0 * UPL + lc_u] = u1;
+    sU[1 * UPL + lc_u] = v1;
+    sU[2 * UPL + lc_u] = w1;
+    sU[3 * UPL + lc_u] = t1;
+    if (has_prow) sP[prow_dst] = ld_prow ? Pg[off_prow + k0 * Z] : 0.0;
+    sU[urow_dst] = ld_urow ? URg[off_urow + k0 * Z] : 0.0;
+    if (has_col) (col_f == FP ? sP : sU)[col_lds] = ld_col ? COLg[off_col + k0 * Z] : 0.0;
+
+    // Loads run two planes ahead: what the iteration for plane k needs from
+    // memory (queue heads p(k+2), uvwT(k+1), halo strips of plane k+1) is
+    // issued while plane k-2 is computed.  Two register sets alternate.
+    struct InFlight {
+        double p, u, v, w, t, prow, urow, col;
+    };
+    auto issue = [&](InFlight& F, int k) __attribute__((always_inline)) {
+        if (active) {
+            if (k + 2 < d.nk) F.p = Pg[off_c + (k + 2) * Z];
+            if (k + 1 < d.nk) {
+                F.u = Ug[off_c + (k + 1) * Z];
+                F.v = Vg[off_c + (k + 1) * Z];
+                F.w = Wg[off_c + (k + 1) * Z];
+                F.t = Tg[off_c + (k + 1) * Z];
+            }
+        }
+        if (k + 1 < k1) {
+            if (ld_prow) F.prow = Pg[off_prow + (k + 1) * Z];
+            if (ld_urow) F.urow = URg[off_urow + (k + 1) * Z];
+            if (ld_col) F.col = COLg[off_col + (k + 1) * Z];
+        }
+    };
+    InFlight X{0, 0, 0, 0, 0, 0, 0, 0}, Y{0, 0, 0, 0, 0, 0, 0, 0};
+    issue(X, k0);
+    if (k0 + 1 < k1) issue(Y, k0 + 1);
+    __syncthreads();
 
     double acc[NF] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const int lc_p = (row + 2) * PW + lane + 2;                 // this cell in sP
-    const int lc_u = (row + 1) * UW + lane + 1;                 // this cell in sU planes
+    int buf = 0;
 
-    for (int k = k0; k < k1; ++k) {
-        __syncthreads();                                        // plane k-1 fully consumed
-        sP[lc_p] = p2;
-        sU[0 * UPL + lc_u] = u1;
-        sU[1 * UPL + lc_u] = v1;
-        sU[2 * UPL + lc_u] = w1;
-        sU[3 * UPL + lc_u] = t1;
-        if (has_prow) sP[prow_lds * PW + lane + 2] = r_prow;
-        if (has_urow) sU[urow_f * UPL + urow_lds * UW + lane + 1] = r_urow;
-        if (has_col) (col_f == FP ? sP : sU)[col_lds] = r_col;
-        __syncthreads();
-
-        const double p4 = np_, u2 = nu_, v2 = nv_, w2 = nw_, t2 = nt_;
-        if (k + 1 < k1) {                                       // prefetch for plane k+1
-            const int kz = (k + 1) * Z;
-            if (present) {
-                np_ = Pg[off_c + kz + 2 * Z];
-                nu_ = Ug[off_c + kz + Z];
-                nv_ = Vg[off_c + kz + Z];
-                nw_ = Wg[off_c + kz + Z];
-                nt_ = Tg[off_c + kz + Z];
-            }
-            if (has_prow) r_prow = Pg[off_prow + kz];
-            if (has_urow) r_urow = URg[off_urow + kz];
-            if (has_col) r_col = COLg[off_col + kz];
+    auto plane = [&](InFlight& F, int k) __attribute__((always_inline)) {
+        // complete the queues; planes past the top wall follow the wall rules
+        const double p4 = k + 2 < d.nk ? F.p : 2.0 * p3 - p2;
+        const bool in1 = k + 1 < d.nk;
+        const double u2 = in1 ? F.u : -u1, v2 = in1 ? F.v : -v1, w2 = in1 ? F.w : -w1, t2 = in1 ? F.t : t1;
+        if (k + 1 < k1) {
+            // plane k+1 into the other LDS buffer (its last readers finished
+            // before the barrier that ended the previous plane)
+            double* const nP = sP + (buf ^ 1) * PPL;
+            double* const nU = sU + (buf ^ 1) * 4 * UPL;
+            nP[lc_p] = p3;
+            nU[0 * UPL + lc_u] = u2;
+            nU[1 * UPL + lc_u] = v2;
+            nU[2 * UPL + lc_u] = w2;
+            nU[3 * UPL + lc_u] = t2;
+            if (has_prow) nP[prow_dst] = F.prow;
+            nU[urow_dst] = F.urow;
+            if (has_col) (col_f == FP ? nP : nU)[col_lds] = F.col;
         }
+        if (k + 2 < k1) issue(F, k + 2);
 
+        double* const cP = sP + buf * PPL;
+        double* const cU = sU + buf * 4 * UPL;
+        if (bnd) {
+            fix_ghosts(cP, cU);
+            __syncthreads();
+        }
         if (active) {
             Star s;
             s.p = p2;
-            s.pxm = sP[lc_p - 1]; s.pxp = sP[lc_p + 1]; s.pxm2 = sP[lc_p - 2]; s.pxp2 = sP[lc_p + 2];
-            s.pym = sP[lc_p - PW]; s.pyp = sP[lc_p + PW]; s.pym2 = sP[lc_p - 2 * PW]; s.pyp2 = sP[lc_p + 2 * PW];
+            s.pxm = cP[lc_p - 1]; s.pxp = cP[lc_p + 1]; s.pxm2 = cP[lc_p - 2]; s.pxp2 = cP[lc_p + 2];
+            s.pym = cP[lc_p - PW]; s.pyp = cP[lc_p + PW]; s.pym2 = cP[lc_p - 2 * PW]; s.pyp2 = cP[lc_p + 2 * PW];
             s.pzm = p1; s.pzp = p3; s.pzm2 = p0; s.pzp2 = p4;
-#define STAR_LDS(nm, plane, c0, cm, cp)                                            \
+#define STAR_LDS(nm, pl, c0, cm, cp)                                               \
             s.nm = c0; s.nm##zm = cm; s.nm##zp = cp;                               \
-            s.nm##xm = sU[plane * UPL + lc_u - 1]; s.nm##xp = sU[plane * UPL + lc_u + 1]; \
-            s.nm##ym = sU[plane * UPL + lc_u - UW]; s.nm##yp = sU[plane * UPL + lc_u + UW];
+            s.nm##xm = cU[pl * UPL + lc_u - 1]; s.nm##xp = cU[pl * UPL + lc_u + 1]; \
+            s.nm##ym = cU[pl * UPL + lc_u - UW]; s.nm##yp = cU[pl * UPL + lc_u + UW];
             STAR_LDS(u, 0, u1, u0, u2)
             STAR_LDS(v, 1, v1, v0, v2)
             STAR_LDS(w, 2, w1, w0, w2)
@@ -274,8 +468,15 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef c, Sw
                 for (int f = 0; f < NF; ++f) acc[f] = fma(R[f], R[f], acc[f]);
             }
         }
+        __syncthreads();
+        buf ^= 1;
         p0 = p1; p1 = p2; p2 = p3; p3 = p4;
         u0 = u1; u1 = u2; v0 = v1; v1 = v2; w0 = w1; w1 = w2; t0 = t1; t1 = t2;
+    };
+
+    for (int k = k0; k < k1; k += 2) {
+        plane(X, k);
+        if (k + 1 < k1) plane(Y, k + 1);
     }
 
     if (NORM) {

@@ -349,3 +349,31 @@ def test_bc_exact_for_compatible_fields(orc):
         face_z = (np.r_[0:NG, -NG:0], slice(NG, -NG), slice(NG, -NG))
         for sl in (face_x, face_y, face_z):
             np.testing.assert_allclose(g[sl], e[sl], rtol=0, atol=1e-14, err_msg=O.FIELDS[f])
+
+
+# --------------------------------------------------------------------------
+# Hot-wall Nusselt number: the one-sided second-order wall gradient is exact
+# for profiles quadratic in x, so pure conduction gives Nu = 1 and
+# T = 1 - x + a x (1 - x) gives Nu = 1 - a (dT/dx at the wall is a - 1).
+@pytest.mark.parametrize("a", [0.0, 0.3, -0.7])
+def test_nusselt_exact_for_quadratic_profiles(orc, a):
+    P = O.Problem(12, 7, 9)
+    q = P.zeros()
+    x, y, z = grids(P)
+    set_interior(P, q, 4, 1.0 - x + a * x * (1.0 - x) + 0.0 * y * z)
+    assert abs(O.nusselt_hot(P, q) - (1.0 - a)) < 1e-12
+
+
+def test_nusselt_scales_with_wall_difference_and_field(orc):
+    """Nu is relative to t_hot - t_cold, and a per-(j,k) hot-wall field
+    enters through its mean for a conduction profile."""
+    P = O.Problem(10, 6, 5, t_hot=3.0, t_cold=1.0)
+    q = P.zeros()
+    x, _, _ = grids(P)
+    set_interior(P, q, 4, 3.0 - 2.0 * x)
+    assert abs(O.nusselt_hot(P, q) - 1.0) < 1e-12
+    field = np.full(P.nj * P.nk, 3.0)
+    field[::2] = 3.5
+    P2 = O.Problem(10, 6, 5, t_hot=3.0, t_cold=1.0, t_hot_field=field)
+    expect = 1.0 + 8.0 * (field.mean() - 3.0) / (3.0 / P.ni) / 2.0
+    assert abs(O.nusselt_hot(P2, q) - expect) < 1e-12
