@@ -15,14 +15,17 @@
  * Conventions shared by every call
  *   - State layout.  q is ONE allocation of 5 fields in the order
  *     p, u, v, w, T (Listing 2: var 1 is pressure, vars 2..5 the velocities
- *     and temperature).  Field f, cell (i, j, k) lives at
- *         q[((f*(nk+2g) + (k+g))*(nj+2g) + (j+g))*(ni+2g) + (i+g)]
+ *     and temperature), i fastest and k slowest (Sec. 3.1), (i,j,k) = (x,y,z),
  *     with g = ng = 2 ghost layers per side (Listing 1: "interior cell index
- *     starts at 3"), i fastest and k slowest (Sec. 3.1), (i,j,k) = (x,y,z).
- *     Interior cells are 0 <= i < ni etc.  cavity_init also fills the face
- *     ghost layers; cavity_step never reads a ghost cell (their contents
- *     after a step are unspecified).
- *     Element type: double when dtype == CAV_F64.
+ *     starts at 3").  Rows are padded so that every interior row starts on
+ *     a 128-byte boundary (when q is 128-byte aligned): field f, cell
+ *     (i, j, k) with -2 <= i < ni+2 etc. lives at element
+ *         f*sf + (k+2)*sk + (j+2)*sj + lead + i
+ *     with lead = 16, sj = (lead + ni + 2) rounded up to a multiple of 16,
+ *     sk = (nj+4)*sj, sf = (nk+4)*sk (cavity_layout returns them).  Interior
+ *     cells are 0 <= i < ni etc.  cavity_init also fills the face ghost
+ *     layers; cavity_step never reads a ghost cell (their contents after a
+ *     step are unspecified).  Element type: double when dtype == CAV_F64.
  *   - Pointers are DEVICE pointers unless the comment says (host).  The
  *     caller owns every buffer; the library allocates no device memory and
  *     keeps no pointer after a call returns.
@@ -87,8 +90,17 @@ typedef struct {
     int32_t width[5];
 } cav_halo;
 
-/* Number of elements of one state array (all 5 fields, ghosts included):
- * 5*(ni+2ng)*(nj+2ng)*(nk+2ng).  Returns 0 for an invalid grid. */
+/* Element strides of the state layout (see "State layout" above):
+ * cell (f, i, j, k) is at origin + f*sf + k*sk + j*sj + i, where
+ * origin = 2*sk + 2*sj + lead is the element of interior cell (0, 0, 0). */
+typedef struct {
+    int64_t lead, sj, sk, sf, origin;
+} cav_layout;
+
+int cavity_layout(const cav_grid* grid, cav_layout* out);
+
+/* Number of elements of one state array (all 5 fields, ghosts and row
+ * padding included): 5*sf.  Returns 0 for an invalid grid. */
 size_t cavity_state_elems(const cav_grid* grid);
 
 /* Bytes of the workspace `ws` that cavity_step and cavity_residual_norm

@@ -15,7 +15,7 @@ from dataclasses import dataclass, field
 from typing import Optional, Sequence, Tuple
 
 from ._lib import (CAV_EHIP, CAV_EINVAL, CAV_ENONFINITE, CAV_ENOSYS, CAV_ESIZE, CAV_F64, CAV_OK,
-                   EXPORTS, CavError, CavGrid, CavHalo, CavKernelTime, CavParams, check, lib)
+                   EXPORTS, CavError, CavGrid, CavHalo, CavKernelTime, CavLayout, CavParams, check, lib)
 
 NG = 2
 FIELDS = ("p", "u", "v", "w", "T")
@@ -108,6 +108,22 @@ def _params(p):
 
 
 # ---- the C ABI, name for name ------------------------------------------------
+
+def cavity_layout(grid) -> CavLayout:
+    out = CavLayout()
+    check(lib().cavity_layout(ctypes.byref(_grid(grid)), ctypes.byref(out)))
+    return out
+
+
+def state_view(grid, q):
+    """(5, nk+4, nj+4, ni+4) strided view of a flat state tensor in the
+    library layout (cells and ghosts; the row padding is skipped)."""
+    import torch
+    g = grid if isinstance(grid, Grid) else Grid(grid.ni, grid.nj, grid.nk, grid.ng, grid.dtype)
+    L = cavity_layout(g)
+    return torch.as_strided(q, (5, g.nk + 2 * g.ng, g.nj + 2 * g.ng, g.ni + 2 * g.ng),
+                            (L.sf, L.sk, L.sj, 1), q.storage_offset() + L.lead - g.ng)
+
 
 def cavity_state_elems(grid) -> int:
     return int(lib().cavity_state_elems(ctypes.byref(_grid(grid))))
@@ -215,14 +231,14 @@ class Cavity:
     def norms(self):
         return cavity_residual_norm(self.grid, self.ws)
 
-    def fields(self):
-        """The state as a (5, nk+4, nj+4, ni+4) view."""
-        return self.q.view(*self.grid.shape)
+    def fields(self, which=None):
+        """A state as a (5, nk+4, nj+4, ni+4) strided view (default: q)."""
+        return state_view(self.grid, self.q if which is None else which)
 
     def interior(self):
         g = self.grid.ng
         return self.fields()[:, g:g + self.grid.nk, g:g + self.grid.nj, g:g + self.grid.ni]
 
 
-__all__ = ["Grid", "Params", "Halo", "Cavity", "CavError", "FIELDS", "NG", "EXPORTS",
+__all__ = ["Grid", "Params", "Halo", "Cavity", "CavError", "FIELDS", "NG", "EXPORTS", "state_view",
            "CAV_OK", "CAV_EINVAL", "CAV_ESIZE", "CAV_EHIP", "CAV_ENONFINITE", "CAV_ENOSYS"] + list(EXPORTS)

@@ -22,7 +22,7 @@ ERROR_NAMES = {CAV_EINVAL: "CAV_EINVAL", CAV_ESIZE: "CAV_ESIZE", CAV_EHIP: "CAV_
                CAV_ENONFINITE: "CAV_ENONFINITE", CAV_ENOSYS: "CAV_ENOSYS"}
 
 # every function include/cavity.h declares
-EXPORTS = ("cavity_state_elems", "cavity_workspace_bytes", "halo_buffer_bytes", "cavity_init",
+EXPORTS = ("cavity_layout", "cavity_state_elems", "cavity_workspace_bytes", "halo_buffer_bytes", "cavity_init",
            "cavity_step", "halo_pack", "halo_unpack", "cavity_residual_norm", "cavity_adjoint_step",
            "cavity_last_error", "cavity_timing_enable", "cavity_timing_read")
 
@@ -41,6 +41,11 @@ class CavParams(ctypes.Structure):
 
 class CavHalo(ctypes.Structure):
     _fields_ = [("split", ctypes.c_int32 * 3), ("width", ctypes.c_int32 * 5)]
+
+
+class CavLayout(ctypes.Structure):
+    _fields_ = [("lead", ctypes.c_int64), ("sj", ctypes.c_int64), ("sk", ctypes.c_int64),
+                ("sf", ctypes.c_int64), ("origin", ctypes.c_int64)]
 
 
 class CavKernelTime(ctypes.Structure):
@@ -67,6 +72,8 @@ def lib():
     vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
     G, Pp, H = ctypes.POINTER(CavGrid), ctypes.POINTER(CavParams), ctypes.POINTER(CavHalo)
     dp = ctypes.POINTER(ctypes.c_double)
+    L.cavity_layout.restype = ctypes.c_int
+    L.cavity_layout.argtypes = [G, ctypes.POINTER(CavLayout)]
     L.cavity_state_elems.restype = sz
     L.cavity_state_elems.argtypes = [G]
     L.cavity_workspace_bytes.restype = sz

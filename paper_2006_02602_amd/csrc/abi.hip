@@ -80,7 +80,9 @@ int check_grid(const cav_grid* g)
     if (g->dtype != CAV_F64) return fail(CAV_EINVAL, "unknown dtype %d", g->dtype);
     if (g->ni < 2 || g->nj < 2 || g->nk < 2)
         return fail(CAV_EINVAL, "every grid extent must be >= 2 (got %d x %d x %d)", g->ni, g->nj, g->nk);
-    const long long per = (long long)(g->ni + 2 * NG) * (g->nj + 2 * NG) * (g->nk + 2 * NG);
+    const long long align = ROW_ALIGN_BYTES / (int)sizeof(double);
+    const long long row = (LEAD + (long long)g->ni + NG + align - 1) / align * align;
+    const long long per = row * (g->nj + 2 * NG) * (g->nk + 2 * NG);
     if (per >= (1LL << 31))
         return fail(CAV_EINVAL, "grid %d x %d x %d too large (one field must stay below 2^31 elements)",
                     g->ni, g->nj, g->nk);
@@ -93,7 +95,8 @@ Dims dims_of(const cav_grid* g)
     d.ni = g->ni;
     d.nj = g->nj;
     d.nk = g->nk;
-    d.sy = g->ni + 2 * NG;
+    const int align = ROW_ALIGN_BYTES / (int)sizeof(double);
+    d.sy = (LEAD + g->ni + NG + align - 1) / align * align;
     d.sz = (g->nj + 2 * NG) * d.sy;
     return d;
 }
@@ -222,6 +225,20 @@ size_t cavity_state_elems(const cav_grid* grid)
 {
     if (check_grid(grid) != CAV_OK) return 0;
     return (size_t)NF * field_elems(dims_of(grid));
+}
+
+int cavity_layout(const cav_grid* grid, cav_layout* out)
+{
+    int rc;
+    if ((rc = check_grid(grid))) return rc;
+    if (!out) return fail(CAV_EINVAL, "out is NULL");
+    const Dims d = dims_of(grid);
+    out->lead = LEAD;
+    out->sj = d.sy;
+    out->sk = d.sz;
+    out->sf = (int64_t)field_elems(d);
+    out->origin = (int64_t)NG * d.sz + (int64_t)NG * d.sy + LEAD;
+    return CAV_OK;
 }
 
 size_t cavity_workspace_bytes(const cav_grid* grid)

@@ -21,15 +21,21 @@ struct CState {
     const double* f[NF];
 };
 
+// Padded state layout: every interior row starts on a 128-byte boundary
+// (LEAD elements into its row), rows and planes are multiples of 128 bytes.
+// Cell (i, j, k) of a field sits at (k+NG)*sz + (j+NG)*sy + LEAD + i.
+constexpr int ROW_ALIGN_BYTES = 128;
+constexpr int LEAD = ROW_ALIGN_BYTES / (int)sizeof(double);   // 16 doubles, NG of them ghosts
+
 struct Dims {
     int ni, nj, nk;
-    int sy;     // ni + 2*NG
-    int sz;     // (nj + 2*NG) * sy
+    int sy;     // row pitch: LEAD + ni + NG rounded up to 128 bytes
+    int sz;     // plane pitch: (nj + 2*NG) * sy
 };
 
 __host__ __device__ inline int cell_off(const Dims& d, int i, int j, int k)
 {
-    return (k + NG) * d.sz + (j + NG) * d.sy + (i + NG);
+    return (k + NG) * d.sz + (j + NG) * d.sy + (i + LEAD);
 }
 
 // Per-cell coefficients of the residual (all derived on the host).

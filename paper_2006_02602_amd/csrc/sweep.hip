@@ -457,12 +457,13 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef c, Sw
 #undef STAR_LDS
             double R[NF], dt;
             cell_residual(c, s, R, dt);
+            // the new state is not read again by this launch: stream it out
             const int o = off_c + k * Z;
-            qn.f[FP][o] = fma(dt, R[FP], s.p) - pc_new;
-            qn.f[FU][o] = fma(dt, R[FU], s.u);
-            qn.f[FV][o] = fma(dt, R[FV], s.v);
-            qn.f[FW][o] = fma(dt, R[FW], s.w);
-            qn.f[FT][o] = fma(dt, R[FT], s.t);
+            __builtin_nontemporal_store(fma(dt, R[FP], s.p) - pc_new, &qn.f[FP][o]);
+            __builtin_nontemporal_store(fma(dt, R[FU], s.u), &qn.f[FU][o]);
+            __builtin_nontemporal_store(fma(dt, R[FV], s.v), &qn.f[FV][o]);
+            __builtin_nontemporal_store(fma(dt, R[FW], s.w), &qn.f[FW][o]);
+            __builtin_nontemporal_store(fma(dt, R[FT], s.t), &qn.f[FT][o]);
             if (NORM) {
 #pragma unroll
                 for (int f = 0; f < NF; ++f) acc[f] = fma(R[f], R[f], acc[f]);
@@ -510,8 +511,9 @@ SweepGeom sweep_geom(const Dims& d)
     g.tiles_i = (d.ni + SW_TI - 1) / SW_TI;
     g.tiles_j = (d.nj + SW_TJ - 1) / SW_TJ;
     const int tiles = g.tiles_i * g.tiles_j;
-    // aim at ~512 blocks (two 8-wave blocks per CU) with at least 8 planes each
-    const int target = 512;
+    // aim at one round of ~256 blocks (one 8-wave block per CU: the sweep
+    // needs more than 128 VGPRs) with at least 8 planes each
+    const int target = 256;
     int nkc = (target + tiles - 1) / tiles;
     nkc = max(1, min(nkc, (d.nk + 7) / 8));
     g.kc = (d.nk + nkc - 1) / nkc;

@@ -38,10 +38,16 @@ def test_library_exports_every_declared_symbol():
     assert set(decl) <= exported
 
 
-def test_state_and_workspace_sizes():
+def test_state_layout_and_sizes():
+    """Rows padded so interior rows start on 128-byte boundaries."""
     for n in ((2, 2, 2), (16, 16, 16), (67, 37, 21), (256, 256, 256)):
         g = C.Grid(*n)
-        assert C.cavity_state_elems(g) == 5 * (n[0] + 4) * (n[1] + 4) * (n[2] + 4)
+        L = C.cavity_layout(g)
+        assert L.lead == 16 and (L.lead * 8) % 128 == 0
+        assert L.sj % 16 == 0 and L.sj >= L.lead + n[0] + 2 and L.sj < L.lead + n[0] + 2 + 16
+        assert L.sk == (n[1] + 4) * L.sj and L.sf == (n[2] + 4) * L.sk
+        assert L.origin == 2 * L.sk + 2 * L.sj + L.lead
+        assert C.cavity_state_elems(g) == 5 * L.sf
         assert C.cavity_workspace_bytes(g) >= 64 + 40
 
 

@@ -36,14 +36,35 @@ def say(*a):
 
 
 def dev(a):
+    """Flat device copy of a buffer."""
     import torch
     return torch.from_numpy(np.ascontiguousarray(a).reshape(-1)).cuda()
 
 
 def host(t, shape):
+    """Host copy of a flat device buffer."""
     import torch
     torch.cuda.synchronize()
     return t.cpu().numpy().reshape(shape)
+
+
+def put_state(C, g, t, a):
+    """Write a (5, nk+4, nj+4, ni+4) array into state tensor t (library layout)."""
+    import torch
+    C.state_view(g, t).copy_(torch.from_numpy(np.ascontiguousarray(a)))
+
+
+def new_state(C, g, a):
+    import torch
+    t = torch.zeros(C.cavity_state_elems(g), dtype=torch.float64, device="cuda")
+    put_state(C, g, t, a)
+    return t
+
+
+def get_state(C, g, t):
+    import torch
+    torch.cuda.synchronize()
+    return C.state_view(g, t).cpu().numpy()
 
 
 def face_ghost_mask(shape):
@@ -75,7 +96,7 @@ def test_init_bit_exact(C, n):
     P, g, prm = problem(C, n)
     ref = O.init(P, 11, 1e-3)
     cav = C.Cavity(g, prm).init(11, 1e-3)
-    got = host(cav.q, P.shape)
+    got = get_state(C, g, cav.q)
     m = face_ghost_mask(P.shape)
     for f in range(5):
         assert np.array_equal(got[f][m], ref[f][m]), O.FIELDS[f]
@@ -102,7 +123,7 @@ def test_pack_unpack_bit_exact(C, n, split, width):
     g, h = C.Grid(*n), C.Halo(split, width)
     q = np.random.default_rng(hash((n, split, width)) % 2**32).standard_normal(P.shape)
     ref = O.halo_pack(P, (split, width), q)
-    qd = dev(q)
+    qd = new_state(C, g, q)
     nbytes = C.halo_buffer_bytes(g, h)
     assert nbytes == 8 * ref.size
     buf = torch.full((ref.size,), float("nan"), dtype=torch.float64, device="cuda")
@@ -114,12 +135,12 @@ def test_pack_unpack_bit_exact(C, n, split, width):
     O.halo_unpack(P, (split, width), np.ones(ref.size), mark)
     qp = q.copy()
     qp[mark == 1] = np.nan
-    qpd = dev(qp)
+    qpd = new_state(C, g, qp)
     C.halo_unpack(g, h, buf, qpd)
-    assert np.array_equal(host(qpd, P.shape), q)
+    assert np.array_equal(get_state(C, g, qpd), q)
     # and the round trip leaves q bit-identical
     C.halo_unpack(g, h, buf, qd)
-    assert np.array_equal(host(qd, P.shape), q)
+    assert np.array_equal(get_state(C, g, qd), q)
 
 
 # ---------------------------------------------------------------------------
@@ -129,9 +150,9 @@ def run_both(C, n, Ra, steps, seed, halo=None, noise=1e-3, **kw):
     ref = q0.copy()
     nref = O.step(P, ref, steps, halo=halo)
     cav = C.Cavity(g, prm, C.Halo(*halo) if halo else None)
-    cav.q.copy_(dev(q0))
+    put_state(C, g, cav.q, q0)
     cav.step(steps)
-    got = host(cav.q, P.shape)
+    got = get_state(C, g, cav.q)
     ngot = cav.norms()
     return P, P.interior(got), P.interior(ref), np.array(ngot), nref
 
@@ -179,8 +200,7 @@ def test_quiescent_rest_exact(C):
     P, g, prm = problem(C, n, t_hot=0.5, t_cold=0.5, t_inf=0.5)
     cav = C.Cavity(g, prm, C.Halo((2, 1, 1), (2, 1, 1, 1, 1))).init(3, 0.0)
     cav.step(25)
-    I = host(cav.q, P.shape)
-    I = P.interior(I)
+    I = P.interior(get_state(C, g, cav.q))
     assert np.all(I[:4] == 0.0) and np.all(I[4] == 0.5)
     assert cav.norms() == [0.0] * 5
 
@@ -202,9 +222,9 @@ def test_y_mirror_symmetry_full_size(C):
     say("mirror 256^3 x200")
     P, g, prm = problem(C, (256, 256, 256), Ra=1e5)
     cav = C.Cavity(g, prm, C.Halo((2, 2, 2), (1, 2, 2, 2, 2)))
-    cav.q.copy_(dev(y_symmetric_state(P, 2)))
+    put_state(C, g, cav.q, y_symmetric_state(P, 2))
     cav.step(200)
-    I = P.interior(host(cav.q, P.shape))
+    I = P.interior(get_state(C, g, cav.q))
     for f in range(5):
         s = -1.0 if f == 2 else 1.0
         assert np.array_equal(I[f], s * I[f][:, ::-1, :]), O.FIELDS[f]
@@ -219,11 +239,11 @@ def test_determinism_and_restart(C):
     b = C.Cavity(g, prm, h).init(9)
     a.step(40)
     b.step(17).step(23)
-    assert np.array_equal(P.interior(host(a.q, P.shape)), P.interior(host(b.q, P.shape)))
+    assert np.array_equal(P.interior(get_state(C, g, a.q)), P.interior(get_state(C, g, b.q)))
     assert a.norms() == b.norms()
     c = C.Cavity(g, prm, h).init(9)
     c.step(40)
-    assert np.array_equal(P.interior(host(a.q, P.shape)), P.interior(host(c.q, P.shape)))
+    assert np.array_equal(P.interior(get_state(C, g, a.q)), P.interior(get_state(C, g, c.q)))
 
 
 def test_ghost_cells_never_read(C):
@@ -237,12 +257,13 @@ def test_ghost_cells_never_read(C):
     poisoned = np.full(P.shape, np.nan)
     P.interior(poisoned)[:] = P.interior(q0)
     a, b = C.Cavity(g, prm, h), C.Cavity(g, prm, h)
-    a.q.copy_(dev(q0))
-    b.q.copy_(dev(poisoned))
+    put_state(C, g, a.q, q0)
+    b.q.fill_(float("nan"))
+    put_state(C, g, b.q, poisoned)
     b.q_tmp.fill_(float("nan"))
     a.step(7)
     b.step(7)
-    assert np.array_equal(P.interior(host(a.q, P.shape)), P.interior(host(b.q, P.shape)))
+    assert np.array_equal(P.interior(get_state(C, g, a.q)), P.interior(get_state(C, g, b.q)))
     assert a.norms() == b.norms()
 
 
@@ -253,7 +274,7 @@ def test_poisoned_scratch_is_overwritten(C):
     cav = C.Cavity(g, prm).init(4)
     cav.q_tmp.fill_(float("nan"))
     cav.step(1)
-    I = P.interior(host(cav.q, P.shape))
+    I = P.interior(get_state(C, g, cav.q))
     assert np.all(np.isfinite(I))
 
 
