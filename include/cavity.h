@@ -21,11 +21,13 @@
  *     a 128-byte boundary (when q is 128-byte aligned): field f, cell
  *     (i, j, k) with -2 <= i < ni+2 etc. lives at element
  *         f*sf + (k+2)*sk + (j+2)*sj + lead + i
- *     with lead = 16, sj = (lead + ni + 2) rounded up to a multiple of 16,
+ *     with lead = 128 bytes of elements (16 doubles or 32 floats),
+ *     sj = (lead + ni + 2) rounded up to a multiple of lead,
  *     sk = (nj+4)*sj, sf = (nk+4)*sk (cavity_layout returns them).  Interior
  *     cells are 0 <= i < ni etc.  cavity_init also fills the face ghost
  *     layers; cavity_step never reads a ghost cell (their contents after a
- *     step are unspecified).  Element type: double when dtype == CAV_F64.
+ *     step are unspecified).  Element type: double for CAV_F64, float for
+ *     CAV_F32 (the halo buffer uses the same element type).
  *   - Pointers are DEVICE pointers unless the comment says (host).  The
  *     caller owns every buffer; the library allocates no device memory and
  *     keeps no pointer after a call returns.
@@ -57,14 +59,16 @@ extern "C" {
 #define CAV_ENOSYS    (-5)  /* operation not available in this build           */
 
 /* ---- element types ---------------------------------------------------- */
-#define CAV_F64 0
+#define CAV_F64 0   /* state and stencil arithmetic in FP64                  */
+#define CAV_F32 1   /* state and stencil arithmetic in FP32; residual norms and
+                       the Nusselt integral still accumulate in FP64       */
 
 /* Grid of one cavity (or one GPU's block of it).  ni, nj, nk >= 2 interior
  * cells; ng must be 2 (the pressure stencil reaches two cells, Sec. 3.1). */
 typedef struct {
     int32_t ni, nj, nk;
     int32_t ng;
-    int32_t dtype;          /* CAV_F64 */
+    int32_t dtype;          /* CAV_F64 or CAV_F32 */
 } cav_grid;
 
 /* Physical and numerical parameters (Sec. 2).  Nondimensional, free-fall
@@ -179,6 +183,16 @@ int halo_unpack(const cav_grid* grid, const cav_halo* halo, const void* buf,
  * any norm is NaN or infinite (the values are still written). */
 int cavity_residual_norm(const cav_grid* grid, const void* ws, size_t ws_bytes,
                          double* out5, hipStream_t stream);
+
+/* Mean Nusselt number of the hot wall x = 0 of state q, accumulated in
+ * FP64 (either dtype): the wall heat flux -dT/dx from the second-order
+ * one-sided difference (9 T_0 - T_1 - 8 t_hot) / (3h), h = 1/ni, through the
+ * wall value and the first two cell centres, averaged over the wall and
+ * divided by t_hot - t_cold (Sec. 2: the cavity carries heat between its
+ * hot and cold vertical walls).  q: device, read.  ws: device workspace
+ * (>= cavity_workspace_bytes).  out: HOST, 1 double.  Waits for `stream`. */
+int cavity_nusselt(const cav_grid* grid, const cav_params* prm, const void* q,
+                   void* ws, size_t ws_bytes, double* out, hipStream_t stream);
 
 /* Discrete adjoint of one step (reverse mode) -- not available in this
  * build: always returns CAV_ENOSYS and enqueues nothing. */

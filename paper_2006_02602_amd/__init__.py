@@ -14,7 +14,7 @@ import ctypes
 from dataclasses import dataclass, field
 from typing import Optional, Sequence, Tuple
 
-from ._lib import (CAV_EHIP, CAV_EINVAL, CAV_ENONFINITE, CAV_ENOSYS, CAV_ESIZE, CAV_F64, CAV_OK,
+from ._lib import (CAV_EHIP, CAV_EINVAL, CAV_ENONFINITE, CAV_ENOSYS, CAV_ESIZE, CAV_F32, CAV_F64, CAV_OK,
                    EXPORTS, CavError, CavGrid, CavHalo, CavKernelTime, CavLayout, CavParams, check, lib)
 
 NG = 2
@@ -30,8 +30,13 @@ class Grid:
     dtype: int = CAV_F64
 
     @staticmethod
-    def cube(n: int) -> "Grid":
-        return Grid(n, n, n)
+    def cube(n: int, dtype: int = CAV_F64) -> "Grid":
+        return Grid(n, n, n, NG, dtype)
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float32 if self.dtype == CAV_F32 else torch.float64
 
     def c(self) -> CavGrid:
         return CavGrid(self.ni, self.nj, self.nk, self.ng, self.dtype)
@@ -176,6 +181,16 @@ def cavity_residual_norm(grid, ws, stream=None):
     return [out[i] for i in range(5)]
 
 
+def cavity_nusselt(grid, params, q, ws, stream=None) -> float:
+    """Mean hot-wall Nusselt number of state q (FP64 accumulation)."""
+    qp, _ = _ptr(q)
+    wp, wb = _ptr(ws)
+    out = ctypes.c_double(0.0)
+    check(lib().cavity_nusselt(ctypes.byref(_grid(grid)), ctypes.byref(_params(params)), qp, wp, wb,
+                               ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
 def cavity_adjoint_step(grid, params, q_n, lam_in, lam_out, ws, dj_dthot, dj_dra, stream=None) -> None:
     ptrs = [_ptr(t)[0] for t in (q_n, lam_in, lam_out)]
     wp, wb = _ptr(ws)
@@ -214,11 +229,12 @@ class Cavity:
         n = cavity_state_elems(grid)
         if n == 0:
             raise CavError(CAV_EINVAL, cavity_last_error())
-        self.q = torch.zeros(n, dtype=torch.float64, device=device)
-        self.q_tmp = torch.zeros(n, dtype=torch.float64, device=device)
+        self.q = torch.zeros(n, dtype=grid.torch_dtype, device=device)
+        self.q_tmp = torch.zeros(n, dtype=grid.torch_dtype, device=device)
         self.ws = torch.zeros(cavity_workspace_bytes(grid) // 8, dtype=torch.float64, device=device)
         nb = halo_buffer_bytes(grid, halo) if halo is not None else 0
-        self.buf = torch.zeros(max(1, nb // 8), dtype=torch.float64, device=device) if halo is not None else None
+        es = 4 if grid.dtype == CAV_F32 else 8
+        self.buf = torch.zeros(max(1, nb // es), dtype=grid.torch_dtype, device=device) if halo is not None else None
 
     def init(self, seed: int, noise_amp: float = 1e-3) -> "Cavity":
         cavity_init(self.grid, self.params, seed, noise_amp, self.q)
@@ -231,6 +247,9 @@ class Cavity:
     def norms(self):
         return cavity_residual_norm(self.grid, self.ws)
 
+    def nusselt(self) -> float:
+        return cavity_nusselt(self.grid, self.params, self.q, self.ws)
+
     def fields(self, which=None):
         """A state as a (5, nk+4, nj+4, ni+4) strided view (default: q)."""
         return state_view(self.grid, self.q if which is None else which)
@@ -241,4 +260,4 @@ class Cavity:
 
 
 __all__ = ["Grid", "Params", "Halo", "Cavity", "CavError", "FIELDS", "NG", "EXPORTS", "state_view",
-           "CAV_OK", "CAV_EINVAL", "CAV_ESIZE", "CAV_EHIP", "CAV_ENONFINITE", "CAV_ENOSYS"] + list(EXPORTS)
+           "CAV_OK", "CAV_EINVAL", "CAV_ESIZE", "CAV_EHIP", "CAV_ENONFINITE", "CAV_ENOSYS", "CAV_F64", "CAV_F32"] + list(EXPORTS)

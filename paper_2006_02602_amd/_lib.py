@@ -17,13 +17,14 @@ CAV_EHIP = -3
 CAV_ENONFINITE = -4
 CAV_ENOSYS = -5
 CAV_F64 = 0
+CAV_F32 = 1
 
 ERROR_NAMES = {CAV_EINVAL: "CAV_EINVAL", CAV_ESIZE: "CAV_ESIZE", CAV_EHIP: "CAV_EHIP",
                CAV_ENONFINITE: "CAV_ENONFINITE", CAV_ENOSYS: "CAV_ENOSYS"}
 
 # every function include/cavity.h declares
 EXPORTS = ("cavity_layout", "cavity_state_elems", "cavity_workspace_bytes", "halo_buffer_bytes", "cavity_init",
-           "cavity_step", "halo_pack", "halo_unpack", "cavity_residual_norm", "cavity_adjoint_step",
+           "cavity_step", "halo_pack", "halo_unpack", "cavity_residual_norm", "cavity_nusselt", "cavity_adjoint_step",
            "cavity_last_error", "cavity_timing_enable", "cavity_timing_read")
 
 
@@ -90,6 +91,8 @@ def lib():
     L.halo_unpack.argtypes = [G, H, vp, sz, vp, vp]
     L.cavity_residual_norm.restype = ctypes.c_int
     L.cavity_residual_norm.argtypes = [G, vp, sz, dp, vp]
+    L.cavity_nusselt.restype = ctypes.c_int
+    L.cavity_nusselt.argtypes = [G, Pp, vp, vp, sz, dp, vp]
     L.cavity_adjoint_step.restype = ctypes.c_int
     L.cavity_adjoint_step.argtypes = [G, Pp, vp, vp, vp, vp, sz, vp, vp, vp]
     L.cavity_last_error.restype = ctypes.c_char_p

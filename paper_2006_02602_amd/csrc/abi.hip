@@ -73,15 +73,17 @@ int hip_fail(const char* what, hipError_t e)
 }
 
 // ---- argument checks ------------------------------------------------------
+int elem_size(int dtype) { return dtype == CAV_F32 ? 4 : 8; }
+
 int check_grid(const cav_grid* g)
 {
     if (!g) return fail(CAV_EINVAL, "grid is NULL");
     if (g->ng != NG) return fail(CAV_EINVAL, "ng must be %d (got %d)", NG, g->ng);
-    if (g->dtype != CAV_F64) return fail(CAV_EINVAL, "unknown dtype %d", g->dtype);
+    if (g->dtype != CAV_F64 && g->dtype != CAV_F32) return fail(CAV_EINVAL, "unknown dtype %d", g->dtype);
     if (g->ni < 2 || g->nj < 2 || g->nk < 2)
         return fail(CAV_EINVAL, "every grid extent must be >= 2 (got %d x %d x %d)", g->ni, g->nj, g->nk);
-    const long long align = ROW_ALIGN_BYTES / (int)sizeof(double);
-    const long long row = (LEAD + (long long)g->ni + NG + align - 1) / align * align;
+    const long long align = ROW_ALIGN_BYTES / elem_size(g->dtype);
+    const long long row = (align + (long long)g->ni + NG + align - 1) / align * align;
     const long long per = row * (g->nj + 2 * NG) * (g->nk + 2 * NG);
     if (per >= (1LL << 31))
         return fail(CAV_EINVAL, "grid %d x %d x %d too large (one field must stay below 2^31 elements)",
@@ -95,26 +97,29 @@ Dims dims_of(const cav_grid* g)
     d.ni = g->ni;
     d.nj = g->nj;
     d.nk = g->nk;
-    const int align = ROW_ALIGN_BYTES / (int)sizeof(double);
-    d.sy = (LEAD + g->ni + NG + align - 1) / align * align;
+    const int align = ROW_ALIGN_BYTES / elem_size(g->dtype);
+    d.lead = align;
+    d.sy = (d.lead + g->ni + NG + align - 1) / align * align;
     d.sz = (g->nj + 2 * NG) * d.sy;
     return d;
 }
 
 size_t field_elems(const Dims& d) { return (size_t)(d.nk + 2 * NG) * (size_t)d.sz; }
 
-State state_of(void* q, const Dims& d)
+template <typename Real>
+StateT<Real> state_of(void* q, const Dims& d)
 {
-    State s;
-    double* base = static_cast<double*>(q);
+    StateT<Real> s;
+    Real* base = static_cast<Real*>(q);
     for (int f = 0; f < NF; ++f) s.f[f] = base + (size_t)f * field_elems(d);
     return s;
 }
 
-CState cstate_of(const void* q, const Dims& d)
+template <typename Real>
+CStateT<Real> cstate_of(const void* q, const Dims& d)
 {
-    CState s;
-    const double* base = static_cast<const double*>(q);
+    CStateT<Real> s;
+    const Real* base = static_cast<const Real*>(q);
     for (int f = 0; f < NF; ++f) s.f[f] = base + (size_t)f * field_elems(d);
     return s;
 }
@@ -212,9 +217,53 @@ int do_halo(const cav_grid* grid, const HaloGeom& hg, void* q, void* buf, bool p
 {
     if (hg.face_blocks == 0 || hg.wsum == 0) return CAV_OK;       // nothing to exchange
     const Dims d = dims_of(grid);
-    hipError_t e = run(pack ? "halo_pack" : "halo_unpack", s,
-                       [&] { return launch_halo(d, hg, state_of(q, d), static_cast<double*>(buf), pack, s); });
+    hipError_t e = run(pack ? "halo_pack" : "halo_unpack", s, [&] {
+        return grid->dtype == CAV_F32
+                   ? launch_halo<float>(d, hg, state_of<float>(q, d), static_cast<float*>(buf), pack, s)
+                   : launch_halo<double>(d, hg, state_of<double>(q, d), static_cast<double*>(buf), pack, s);
+    });
     return e == hipSuccess ? CAV_OK : hip_fail(pack ? "halo_pack launch" : "halo_unpack launch", e);
+}
+
+// The pseudo-time steps of cavity_step in element type Real.
+template <typename Real>
+int step_impl(const cav_grid* grid, const cav_params* prm, const cav_halo* halo, const HaloGeom& hg, void* q,
+              void* q_tmp, void* ws, void* halo_buf, int32_t nsteps, hipStream_t stream)
+{
+    int rc;
+    const Dims d = dims_of(grid);
+    const Coef c = coef_of(grid, prm);
+    const SweepGeom g = sweep_geom(d);
+    double* wsd = static_cast<double*>(ws);
+    double* partials = reinterpret_cast<double*>(static_cast<char*>(ws) + WS_HEAD);
+    void* cur = q;
+    void* nxt = q_tmp;
+    hipError_t e;
+    for (int n = 0; n < nsteps; ++n) {
+        // the wall ghosts are derived inside the sweep; no separate pass
+        if (halo) {
+            if ((rc = do_halo(grid, hg, cur, halo_buf, true, stream))) return rc;
+            if ((rc = do_halo(grid, hg, cur, halo_buf, false, stream))) return rc;
+        }
+        const bool last = n == nsteps - 1;
+        e = run(last ? "sweep_norm" : "sweep", stream, [&] {
+            return launch_sweep<Real>(d, c, g, cstate_of<Real>(cur, d), state_of<Real>(nxt, d), partials, last,
+                                      stream);
+        });
+        if (e != hipSuccess) return hip_fail("sweep launch", e);
+        void* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    const double ncell = (double)d.ni * d.nj * d.nk;
+    e = run("norm_finalize", stream, [&] { return launch_norm_finalize(partials, g.nblocks, ncell, wsd, stream); });
+    if (e != hipSuccess) return hip_fail("norm finalize launch", e);
+    if (cur != q) {
+        const size_t bytes = (size_t)NF * field_elems(d) * sizeof(Real);
+        e = run("copy", stream, [&] { return hipMemcpyAsync(q, cur, bytes, hipMemcpyDeviceToDevice, stream); });
+        if (e != hipSuccess) return hip_fail("state copy", e);
+    }
+    return CAV_OK;
 }
 
 }  // namespace
@@ -233,11 +282,11 @@ int cavity_layout(const cav_grid* grid, cav_layout* out)
     if ((rc = check_grid(grid))) return rc;
     if (!out) return fail(CAV_EINVAL, "out is NULL");
     const Dims d = dims_of(grid);
-    out->lead = LEAD;
+    out->lead = d.lead;
     out->sj = d.sy;
     out->sk = d.sz;
     out->sf = (int64_t)field_elems(d);
-    out->origin = (int64_t)NG * d.sz + (int64_t)NG * d.sy + LEAD;
+    out->origin = (int64_t)NG * d.sz + (int64_t)NG * d.sy + d.lead;
     return CAV_OK;
 }
 
@@ -251,7 +300,7 @@ size_t halo_buffer_bytes(const cav_grid* grid, const cav_halo* halo)
 {
     HaloGeom hg;
     if (check_grid(grid) != CAV_OK || check_halo(grid, halo, &hg) != CAV_OK) return 0;
-    return halo_elems(hg) * sizeof(double);
+    return halo_elems(hg) * (size_t)elem_size(grid->dtype);
 }
 
 int cavity_init(const cav_grid* grid, const cav_params* prm, uint64_t seed, double noise_amp, void* q,
@@ -262,11 +311,17 @@ int cavity_init(const cav_grid* grid, const cav_params* prm, uint64_t seed, doub
     if (!q) return fail(CAV_EINVAL, "q is NULL");
     if (!std::isfinite(noise_amp)) return fail(CAV_EINVAL, "noise_amp must be finite");
     const Dims d = dims_of(grid);
-    const State s = state_of(q, d);
-    hipError_t e = run("init", stream, [&] { return launch_init(d, prm->t_hot, prm->t_cold, seed, noise_amp, s, stream); });
-    if (e != hipSuccess) return hip_fail("init launch", e);
     const Bcs bc{prm->t_hot, prm->t_cold};
-    e = run("bc", stream, [&] { return launch_bc(d, bc, s, stream); });
+    const bool f32 = grid->dtype == CAV_F32;
+    hipError_t e = run("init", stream, [&] {
+        return f32 ? launch_init<float>(d, prm->t_hot, prm->t_cold, seed, noise_amp, state_of<float>(q, d), stream)
+                   : launch_init<double>(d, prm->t_hot, prm->t_cold, seed, noise_amp, state_of<double>(q, d), stream);
+    });
+    if (e != hipSuccess) return hip_fail("init launch", e);
+    e = run("bc", stream, [&] {
+        return f32 ? launch_bc<float>(d, bc, state_of<float>(q, d), stream)
+                   : launch_bc<double>(d, bc, state_of<double>(q, d), stream);
+    });
     if (e != hipSuccess) return hip_fail("bc launch", e);
     return CAV_OK;
 }
@@ -286,43 +341,13 @@ int cavity_step(const cav_grid* grid, const cav_params* prm, const cav_halo* hal
     HaloGeom hg;
     if (halo) {
         if ((rc = check_halo(grid, halo, &hg))) return rc;
-        const size_t need = halo_elems(hg) * sizeof(double);
+        const size_t need = halo_elems(hg) * (size_t)elem_size(grid->dtype);
         if (need && !halo_buf) return fail(CAV_EINVAL, "halo_buf is NULL");
         if (halo_bytes < need) return fail(CAV_ESIZE, "halo_bytes %zu < required %zu", halo_bytes, need);
     }
     if (nsteps == 0) return CAV_OK;
-
-    const Coef c = coef_of(grid, prm);
-    const SweepGeom g = sweep_geom(d);
-    double* wsd = static_cast<double*>(ws);
-    double* partials = reinterpret_cast<double*>(static_cast<char*>(ws) + WS_HEAD);
-    void* cur = q;
-    void* nxt = q_tmp;
-    hipError_t e;
-    for (int n = 0; n < nsteps; ++n) {
-        // the wall ghosts are derived inside the sweep; no separate pass
-        if (halo) {
-            if ((rc = do_halo(grid, hg, cur, halo_buf, true, stream))) return rc;
-            if ((rc = do_halo(grid, hg, cur, halo_buf, false, stream))) return rc;
-        }
-        const bool last = n == nsteps - 1;
-        e = run(last ? "sweep_norm" : "sweep", stream, [&] {
-            return launch_sweep(d, c, g, cstate_of(cur, d), state_of(nxt, d), partials, last, stream);
-        });
-        if (e != hipSuccess) return hip_fail("sweep launch", e);
-        void* t = cur;
-        cur = nxt;
-        nxt = t;
-    }
-    const double ncell = (double)d.ni * d.nj * d.nk;
-    e = run("norm_finalize", stream, [&] { return launch_norm_finalize(partials, g.nblocks, ncell, wsd, stream); });
-    if (e != hipSuccess) return hip_fail("norm finalize launch", e);
-    if (cur != q) {
-        const size_t bytes = (size_t)NF * field_elems(d) * sizeof(double);
-        e = run("copy", stream, [&] { return hipMemcpyAsync(q, cur, bytes, hipMemcpyDeviceToDevice, stream); });
-        if (e != hipSuccess) return hip_fail("state copy", e);
-    }
-    return CAV_OK;
+    return grid->dtype == CAV_F32 ? step_impl<float>(grid, prm, halo, hg, q, q_tmp, ws, halo_buf, nsteps, stream)
+                                  : step_impl<double>(grid, prm, halo, hg, q, q_tmp, ws, halo_buf, nsteps, stream);
 }
 
 int halo_pack(const cav_grid* grid, const cav_halo* halo, const void* q, void* buf, size_t buf_bytes,
@@ -331,7 +356,7 @@ int halo_pack(const cav_grid* grid, const cav_halo* halo, const void* q, void* b
     int rc;
     HaloGeom hg;
     if ((rc = check_grid(grid)) || (rc = check_halo(grid, halo, &hg))) return rc;
-    const size_t need = halo_elems(hg) * sizeof(double);
+    const size_t need = halo_elems(hg) * (size_t)elem_size(grid->dtype);
     if (!q || (need && !buf)) return fail(CAV_EINVAL, "q and buf must not be NULL");
     if (buf_bytes < need) return fail(CAV_ESIZE, "buf_bytes %zu < required %zu", buf_bytes, need);
     return do_halo(grid, hg, const_cast<void*>(q), buf, true, stream);
@@ -343,7 +368,7 @@ int halo_unpack(const cav_grid* grid, const cav_halo* halo, const void* buf, siz
     int rc;
     HaloGeom hg;
     if ((rc = check_grid(grid)) || (rc = check_halo(grid, halo, &hg))) return rc;
-    const size_t need = halo_elems(hg) * sizeof(double);
+    const size_t need = halo_elems(hg) * (size_t)elem_size(grid->dtype);
     if (!q || (need && !buf)) return fail(CAV_EINVAL, "q and buf must not be NULL");
     if (buf_bytes < need) return fail(CAV_ESIZE, "buf_bytes %zu < required %zu", buf_bytes, need);
     return do_halo(grid, hg, q, const_cast<void*>(buf), false, stream);
@@ -362,6 +387,30 @@ int cavity_residual_norm(const cav_grid* grid, const void* ws, size_t ws_bytes, 
     if (e != hipSuccess) return hip_fail("stream synchronize", e);
     for (int f = 0; f < NF; ++f)
         if (!std::isfinite(out5[f])) return fail(CAV_ENONFINITE, "residual norm of field %d is not finite", f);
+    return CAV_OK;
+}
+
+int cavity_nusselt(const cav_grid* grid, const cav_params* prm, const void* q, void* ws, size_t ws_bytes,
+                   double* out, hipStream_t stream)
+{
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_params(prm))) return rc;
+    if (!q || !ws || !out) return fail(CAV_EINVAL, "q, ws and out must not be NULL");
+    if (prm->t_hot == prm->t_cold) return fail(CAV_EINVAL, "t_hot == t_cold: the Nusselt number is undefined");
+    const Dims d = dims_of(grid);
+    const size_t need = ws_bytes_of(d);
+    if (ws_bytes < need) return fail(CAV_ESIZE, "ws_bytes %zu < required %zu", ws_bytes, need);
+    double* slot = static_cast<double*>(ws) + 6;
+    hipError_t e = run("nusselt", stream, [&] {
+        return grid->dtype == CAV_F32
+                   ? launch_nusselt<float>(d, prm->t_hot, prm->t_cold, cstate_of<float>(q, d), slot, stream)
+                   : launch_nusselt<double>(d, prm->t_hot, prm->t_cold, cstate_of<double>(q, d), slot, stream);
+    });
+    if (e != hipSuccess) return hip_fail("nusselt launch", e);
+    e = hipMemcpyAsync(out, slot, sizeof(double), hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return hip_fail("nusselt copy", e);
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail("stream synchronize", e);
     return CAV_OK;
 }
 

@@ -11,31 +11,34 @@ constexpr int NG = 2;       // ghost layers per side
 constexpr int NF = 5;       // fields p, u, v, w, T
 enum Field { FP = 0, FU = 1, FV = 2, FW = 3, FT = 4 };
 
-// Field base pointers of one state array plus its strides (elements).  Cell
-// offsets inside one field fit in 32 bits for every grid this library
-// accepts (checked by the host).
-struct State {
-    double* f[NF];
+// Field base pointers of one state array (element type Real: double for the
+// FP64 form, float for the FP32 form).  Cell offsets inside one field fit in
+// 32 bits for every grid this library accepts (checked by the host).
+template <typename Real>
+struct StateT {
+    Real* f[NF];
 };
-struct CState {
-    const double* f[NF];
+template <typename Real>
+struct CStateT {
+    const Real* f[NF];
 };
 
 // Padded state layout: every interior row starts on a 128-byte boundary
-// (LEAD elements into its row), rows and planes are multiples of 128 bytes.
-// Cell (i, j, k) of a field sits at (k+NG)*sz + (j+NG)*sy + LEAD + i.
+// (lead = 128 bytes of elements into its row), rows and planes are
+// multiples of 128 bytes.  Cell (i, j, k) of a field sits at
+// (k+NG)*sz + (j+NG)*sy + lead + i.
 constexpr int ROW_ALIGN_BYTES = 128;
-constexpr int LEAD = ROW_ALIGN_BYTES / (int)sizeof(double);   // 16 doubles, NG of them ghosts
 
 struct Dims {
     int ni, nj, nk;
-    int sy;     // row pitch: LEAD + ni + NG rounded up to 128 bytes
+    int sy;     // row pitch: lead + ni + NG rounded up to 128 bytes
     int sz;     // plane pitch: (nj + 2*NG) * sy
+    int lead;   // elements before interior cell i = 0 in a row (NG of them ghosts)
 };
 
 __host__ __device__ inline int cell_off(const Dims& d, int i, int j, int k)
 {
-    return (k + NG) * d.sz + (j + NG) * d.sy + (i + LEAD);
+    return (k + NG) * d.sz + (j + NG) * d.sy + (i + d.lead);
 }
 
 // Per-cell coefficients of the residual (all derived on the host).
@@ -79,15 +82,22 @@ struct HaloGeom {
     int face_blocks;          // blocks per (subdomain, face)
 };
 
-// Launchers (return hipGetLastError() of the launch).
-hipError_t launch_bc(const Dims& d, const Bcs& b, State q, hipStream_t s);
+// Launchers (return hipGetLastError() of the launch); Real = double or float.
+template <typename Real>
+hipError_t launch_bc(const Dims& d, const Bcs& b, StateT<Real> q, hipStream_t s);
+template <typename Real>
 hipError_t launch_init(const Dims& d, double t_hot, double t_cold, uint64_t seed, double amp,
-                       State q, hipStream_t s);
-hipError_t launch_sweep(const Dims& d, const Coef& c, const SweepGeom& g, CState q, State qn,
+                       StateT<Real> q, hipStream_t s);
+template <typename Real>
+hipError_t launch_sweep(const Dims& d, const Coef& c, const SweepGeom& g, CStateT<Real> q, StateT<Real> qn,
                         double* partials, bool with_norm, hipStream_t s);
 hipError_t launch_norm_finalize(const double* partials, int nblocks, double ncell, double* out,
                                 hipStream_t s);
-hipError_t launch_halo(const Dims& d, const HaloGeom& h, State q, double* buf, bool pack,
+template <typename Real>
+hipError_t launch_halo(const Dims& d, const HaloGeom& h, StateT<Real> q, Real* buf, bool pack,
                        hipStream_t s);
+template <typename Real>
+hipError_t launch_nusselt(const Dims& d, double t_hot, double t_cold, CStateT<Real> q, double* out,
+                          hipStream_t s);
 
 }  // namespace cav

@@ -27,8 +27,8 @@ __device__ __forceinline__ int cuts_of(int P, int a)
     return (a > 0 ? 1 : 0) + (a < P - 1 ? 1 : 0);
 }
 
-template <bool PACK>
-__global__ __launch_bounds__(256) void halo_kernel(Dims d, HaloGeom h, State q, double* buf)
+template <typename Real, bool PACK>
+__global__ __launch_bounds__(256) void halo_kernel(Dims d, HaloGeom h, StateT<Real> q, Real* buf)
 {
     const int slot = blockIdx.y;
     const int s = slot / 6, face = slot - 6 * s;
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void halo_kernel(Dims d, HaloGeom h, State q, 
         const bool hi2 = f2 & 1;
         if (!(hi2 ? cc[ax2] == h.P[ax2] - 1 : cc[ax2] == 0)) u += h.area[ax2];
     }
-    double* __restrict__ B = buf + u * h.wsum;
+    Real* __restrict__ B = buf + u * h.wsum;
 
     // this thread's tangential cell, the first layer's offset per field and
     // the stride between layers (all fields first, then all stores, so that
@@ -89,11 +89,11 @@ __global__ __launch_bounds__(256) void halo_kernel(Dims d, HaloGeom h, State q, 
             bo[f] = base + (long long)tb * ex + ta;
         }
     }
-    double v0[NF], v1[NF];
+    Real v0[NF], v1[NF];
     if (PACK) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            const double* __restrict__ Q = q.f[f];
+            const Real* __restrict__ Q = q.f[f];
             if (h.w[f] > 0) v0[f] = Q[qo[f]];
             if (h.w[f] > 1) v1[f] = Q[qo[f] + lay_q];
         }
@@ -110,22 +110,25 @@ __global__ __launch_bounds__(256) void halo_kernel(Dims d, HaloGeom h, State q, 
         }
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            double* __restrict__ Q = q.f[f];
+            Real* __restrict__ Q = q.f[f];
             if (h.w[f] > 0) Q[qo[f]] = v0[f];
             if (h.w[f] > 1) Q[qo[f] + lay_q] = v1[f];
         }
     }
 }
 
-hipError_t launch_halo(const Dims& d, const HaloGeom& h, State q, double* buf, bool pack, hipStream_t s)
+template <typename Real>
+hipError_t launch_halo(const Dims& d, const HaloGeom& h, StateT<Real> q, Real* buf, bool pack, hipStream_t s)
 {
     const int nsub = h.P[0] * h.P[1] * h.P[2];
     dim3 grid(h.face_blocks, nsub * 6), block(256);
     if (pack)
-        halo_kernel<true><<<grid, block, 0, s>>>(d, h, q, buf);
+        halo_kernel<Real, true><<<grid, block, 0, s>>>(d, h, q, buf);
     else
-        halo_kernel<false><<<grid, block, 0, s>>>(d, h, q, buf);
+        halo_kernel<Real, false><<<grid, block, 0, s>>>(d, h, q, buf);
     return hipGetLastError();
 }
+template hipError_t launch_halo<double>(const Dims&, const HaloGeom&, StateT<double>, double*, bool, hipStream_t);
+template hipError_t launch_halo<float>(const Dims&, const HaloGeom&, StateT<float>, float*, bool, hipStream_t);
 
 }  // namespace cav

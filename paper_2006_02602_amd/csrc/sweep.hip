@@ -15,25 +15,41 @@
 
 namespace cav {
 
+// Coefficients in the arithmetic type of the sweep.
+template <typename Real>
+struct CoefR {
+    Real hx2, hy2, hz2, ix2, iy2, iz2, eps4, beta2_floor, nu, alpha, t_inf, cfl, dt_visc, t_hot, t_cold;
+};
+
+template <typename Real>
+__device__ __forceinline__ CoefR<Real> coef_as(const Coef& c)
+{
+    return CoefR<Real>{(Real)c.hx2, (Real)c.hy2, (Real)c.hz2, (Real)c.ix2, (Real)c.iy2, (Real)c.iz2,
+                       (Real)c.eps4, (Real)c.beta2_floor, (Real)c.nu, (Real)c.alpha, (Real)c.t_inf,
+                       (Real)c.cfl, (Real)c.dt_visc, (Real)c.t_hot, (Real)c.t_cold};
+}
+
 // ---------------------------------------------------------------------------
 // Per-cell residual.  Inputs: the 13-point pressure star and the 7-point
 // stars of u, v, w, T.  Outputs: R_p (Eq. 1 times beta^2, with the
 // dissipation -eps4 * lambda_x * F_x p / h_x per axis), R_u, R_v, R_w
 // (Eq. 2, advective form, buoyancy +(T - t_inf) along z) and R_T (Eq. 3),
 // and the local pseudo-time step.
+template <typename Real>
 struct Star {
-    double p, pxm, pxp, pxm2, pxp2, pym, pyp, pym2, pyp2, pzm, pzp, pzm2, pzp2;
-    double u, uxm, uxp, uym, uyp, uzm, uzp;
-    double v, vxm, vxp, vym, vyp, vzm, vzp;
-    double w, wxm, wxp, wym, wyp, wzm, wzp;
-    double t, txm, txp, tym, typ, tzm, tzp;
+    Real p, pxm, pxp, pxm2, pxp2, pym, pyp, pym2, pyp2, pzm, pzp, pzm2, pzp2;
+    Real u, uxm, uxp, uym, uyp, uzm, uzp;
+    Real v, vxm, vxp, vym, vyp, vzm, vzp;
+    Real w, wxm, wxp, wym, wyp, wzm, wzp;
+    Real t, txm, txp, tym, typ, tzm, tzp;
 };
 
-__device__ __forceinline__ double lap3(const Coef& c, double q, double xm, double xp, double ym,
-                                       double yp, double zm, double zp)
+template <typename Real>
+__device__ __forceinline__ Real lap3(const CoefR<Real>& c, Real q, Real xm, Real xp, Real ym,
+                                       Real yp, Real zm, Real zp)
 {
     // (L_x + L_y + L_z) q with L_x q = ((q_{i+1} + q_{i-1}) - 2 q_i) / h_x^2
-    return fma(c.ix2, fma(-2.0, q, xp + xm), fma(c.iy2, fma(-2.0, q, yp + ym), c.iz2 * fma(-2.0, q, zp + zm)));
+    return fma(c.ix2, fma(Real(-2), q, xp + xm), fma(c.iy2, fma(Real(-2), q, yp + ym), c.iz2 * fma(Real(-2), q, zp + zm)));
 }
 
 // Square root of a positive argument: hardware reciprocal-square-root
@@ -62,40 +78,51 @@ __device__ __forceinline__ double recip_pos(double x)
     return fma(y, e, y);
 }
 
-__device__ __forceinline__ void cell_residual(const Coef& c, const Star& s, double R[NF], double& dt)
+// FP32 forms: the hardware square root and a reciprocal estimate refined by
+// one Newton step.
+__device__ __forceinline__ float sqrt_pos(float x) { return __builtin_sqrtf(fmaxf(x, 1e-30f)); }
+
+__device__ __forceinline__ float recip_pos(float x)
+{
+    const float y = __builtin_amdgcn_rcpf(x);
+    return fmaf(y, fmaf(-x, y, 1.0f), y);
+}
+
+template <typename Real>
+__device__ __forceinline__ void cell_residual(const CoefR<Real>& c, const Star<Real>& s, Real R[NF], Real& dt)
 {
     // first differences (times 2h)
-    const double dxu = s.uxp - s.uxm, dyu = s.uyp - s.uym, dzu = s.uzp - s.uzm;
-    const double dxv = s.vxp - s.vxm, dyv = s.vyp - s.vym, dzv = s.vzp - s.vzm;
-    const double dxw = s.wxp - s.wxm, dyw = s.wyp - s.wym, dzw = s.wzp - s.wzm;
-    const double dxt = s.txp - s.txm, dyt = s.typ - s.tym, dzt = s.tzp - s.tzm;
-    const double dxp = s.pxp - s.pxm, dyp = s.pyp - s.pym, dzp = s.pzp - s.pzm;
+    const Real dxu = s.uxp - s.uxm, dyu = s.uyp - s.uym, dzu = s.uzp - s.uzm;
+    const Real dxv = s.vxp - s.vxm, dyv = s.vyp - s.vym, dzv = s.vzp - s.vzm;
+    const Real dxw = s.wxp - s.wxm, dyw = s.wyp - s.wym, dzw = s.wzp - s.wzm;
+    const Real dxt = s.txp - s.txm, dyt = s.typ - s.tym, dzt = s.tzp - s.tzm;
+    const Real dxp = s.pxp - s.pxm, dyp = s.pyp - s.pym, dzp = s.pzp - s.pzm;
 
     // advecting velocity scaled by 1/(2h): V . grad q = su*dxq + sv*dyq + sw*dzq
-    const double su = s.u * c.hx2, sv = s.v * c.hy2, sw = s.w * c.hz2;
+    const Real su = s.u * c.hx2, sv = s.v * c.hy2, sw = s.w * c.hz2;
 
     // artificial compressibility and characteristic speeds over h
-    const double u2 = s.u * s.u, v2 = s.v * s.v, w2 = s.w * s.w;
-    const double beta2 = fmax((u2 + v2) + w2, c.beta2_floor);
-    const double b4 = 4.0 * beta2;
-    const double lxn = (fabs(s.u) + sqrt_pos(u2 + b4)) * c.hx2;   // lambda_x / h_x
-    const double lyn = (fabs(s.v) + sqrt_pos(v2 + b4)) * c.hy2;
-    const double lzn = (fabs(s.w) + sqrt_pos(w2 + b4)) * c.hz2;
+    const Real u2 = s.u * s.u, v2 = s.v * s.v, w2 = s.w * s.w;
+    const Real beta2 = fmax((u2 + v2) + w2, c.beta2_floor);
+    const Real b4 = Real(4) * beta2;
+    const Real lxn = (fabs(s.u) + sqrt_pos(u2 + b4)) * c.hx2;   // lambda_x / h_x
+    const Real lyn = (fabs(s.v) + sqrt_pos(v2 + b4)) * c.hy2;
+    const Real lzn = (fabs(s.w) + sqrt_pos(w2 + b4)) * c.hz2;
     dt = c.cfl * fmin(recip_pos((lxn + lyn) + lzn), c.dt_visc);
 
     // continuity (Eq. 1 times beta^2) with fourth-difference dissipation
-    const double div = fma(dxu, c.hx2, fma(dyv, c.hy2, dzw * c.hz2));
-    const double fx = fma(6.0, s.p, fma(-4.0, s.pxp + s.pxm, s.pxp2 + s.pxm2));
-    const double fy = fma(6.0, s.p, fma(-4.0, s.pyp + s.pym, s.pyp2 + s.pym2));
-    const double fz = fma(6.0, s.p, fma(-4.0, s.pzp + s.pzm, s.pzp2 + s.pzm2));
-    const double diss = fma(lxn, fx, fma(lyn, fy, lzn * fz));
+    const Real div = fma(dxu, c.hx2, fma(dyv, c.hy2, dzw * c.hz2));
+    const Real fx = fma(Real(6), s.p, fma(Real(-4), s.pxp + s.pxm, s.pxp2 + s.pxm2));
+    const Real fy = fma(Real(6), s.p, fma(Real(-4), s.pyp + s.pym, s.pyp2 + s.pym2));
+    const Real fz = fma(Real(6), s.p, fma(Real(-4), s.pzp + s.pzm, s.pzp2 + s.pzm2));
+    const Real diss = fma(lxn, fx, fma(lyn, fy, lzn * fz));
     R[FP] = fma(-beta2, div, -c.eps4 * diss);
 
     // momentum (Eq. 2) and energy (Eq. 3)
-    const double adu = fma(su, dxu, fma(sv, dyu, sw * dzu));
-    const double adv = fma(su, dxv, fma(sv, dyv, sw * dzv));
-    const double adw = fma(su, dxw, fma(sv, dyw, sw * dzw));
-    const double adt = fma(su, dxt, fma(sv, dyt, sw * dzt));
+    const Real adu = fma(su, dxu, fma(sv, dyu, sw * dzu));
+    const Real adv = fma(su, dxv, fma(sv, dyv, sw * dzv));
+    const Real adw = fma(su, dxw, fma(sv, dyw, sw * dzw));
+    const Real adt = fma(su, dxt, fma(sv, dyt, sw * dzt));
     R[FU] = fma(c.nu, lap3(c, s.u, s.uxm, s.uxp, s.uym, s.uyp, s.uzm, s.uzp), -fma(dxp, c.hx2, adu));
     R[FV] = fma(c.nu, lap3(c, s.v, s.vxm, s.vxp, s.vym, s.vyp, s.vzm, s.vzp), -fma(dyp, c.hy2, adv));
     R[FW] = fma(c.nu, lap3(c, s.w, s.wxm, s.wxp, s.wym, s.wyp, s.wzm, s.wzp),
@@ -149,21 +176,23 @@ __device__ __forceinline__ Slot make_slot(const Dims& d, int i, int j)
     return s;
 }
 
-__device__ __forceinline__ double ghost_value(int f, int code, double a, double b, const Coef& c)
+template <typename Real>
+__device__ __forceinline__ Real ghost_value(int f, int code, Real a, Real b, const CoefR<Real>& c)
 {
     const int g = code & 3, side = code >> 2;
     if (f == FP) {
-        const double g1 = 2.0 * a - b;
-        return g == 1 ? g1 : 2.0 * g1 - a;
+        const Real g1 = Real(2) * a - b;
+        return g == 1 ? g1 : Real(2) * g1 - a;
     }
-    const double m = g == 1 ? a : b;
-    if (f == FT) return side == SIDE_X_LO ? 2.0 * c.t_hot - m : (side == SIDE_X_HI ? 2.0 * c.t_cold - m : m);
+    const Real m = g == 1 ? a : b;
+    if (f == FT) return side == SIDE_X_LO ? Real(2) * c.t_hot - m : (side == SIDE_X_HI ? Real(2) * c.t_cold - m : m);
     return -m;
 }
 
-__device__ __forceinline__ double slot_load(const double* G, const Slot& s, int kz, int f, const Coef& c)
+template <typename Real>
+__device__ __forceinline__ Real slot_load(const Real* G, const Slot& s, int kz, int f, const CoefR<Real>& c)
 {
-    double v = 0.0;
+    Real v = Real(0);
     if (s.code == 0)
         v = G[s.oa + kz];
     else if (s.code != SLOT_UNUSED)
@@ -173,22 +202,24 @@ __device__ __forceinline__ double slot_load(const double* G, const Slot& s, int 
 
 // Any interior or face-ghost value, straight from global memory (used once
 // per block, for the stars of the centre cell).
-__device__ __forceinline__ double value_at(const Dims& d, const CState& q, const Coef& c, int f, int i, int j,
+template <typename Real>
+__device__ __forceinline__ Real value_at(const Dims& d, const CStateT<Real>& q, const CoefR<Real>& c, int f, int i, int j,
                                            int k)
 {
-    const double* G = q.f[f];
+    const Real* G = q.f[f];
     if (k < 0 || k >= d.nk) {
         const bool lo = k < 0;
         const int g = lo ? -k : k - d.nk + 1;
-        const double a = G[cell_off(d, i, j, lo ? 0 : d.nk - 1)];
-        const double b = G[cell_off(d, i, j, lo ? 1 : d.nk - 2)];
+        const Real a = G[cell_off(d, i, j, lo ? 0 : d.nk - 1)];
+        const Real b = G[cell_off(d, i, j, lo ? 1 : d.nk - 2)];
         return ghost_value(f, g | (SIDE_OTHER << 2), a, b, c);
     }
     return slot_load(G, make_slot(d, i, j), k * d.sz, f, c);
 }
 
-__device__ __forceinline__ void gather_global(const Dims& d, const CState& q, const Coef& c, int i, int j, int k,
-                                              Star& s)
+template <typename Real>
+__device__ __forceinline__ void gather_global(const Dims& d, const CStateT<Real>& q, const CoefR<Real>& c, int i, int j, int k,
+                                              Star<Real>& s)
 {
     auto P = [&](int di, int dj, int dk) { return value_at(d, q, c, FP, i + di, j + dj, k + dk); };
     s.p = P(0, 0, 0);
@@ -222,22 +253,23 @@ __device__ __forceinline__ int xcd_block(int bid, int nb)
 // j row, i along the lanes) marching over a chunk of k planes.  Plane k of
 // all five fields lives in LDS with its i/j halo (2 for p, 1 for the rest);
 // the k neighbours come from per-thread register queues (p: k-2..k+2,
-// others k-1..k+1).  The LDS planes are double-buffered: plane k+1 is
+// others k-1..k+1).  The LDS planes are Real-buffered: plane k+1 is
 // written into one buffer while plane k is computed from the other, so each
 // plane costs one barrier; global loads run two planes ahead.
 // Wall ghosts are derived while loading (Slot), never read from HBM.
-template <bool NORM>
-__global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef c, SweepGeom g, CState q,
-                                                              State qn, double* partials)
+template <typename Real, bool NORM>
+__global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef cd, SweepGeom g, CStateT<Real> q,
+                                                              StateT<Real> qn, double* partials)
 {
     constexpr int TI = SW_TI, TJ = SW_TJ;
     constexpr int PW = TI + 4;              // LDS row pitch, p
     constexpr int UW = TI + 2;              // LDS row pitch, u v w T
     constexpr int PPL = (TJ + 4) * PW;      // LDS plane, p
     constexpr int UPL = (TJ + 2) * UW;      // LDS plane, one of u v w T
-    __shared__ double sP[2 * PPL];
-    __shared__ double sU[2 * 4 * UPL];
+    __shared__ Real sP[2 * PPL];
+    __shared__ Real sU[2 * 4 * UPL];
 
+    const CoefR<Real> c = coef_as<Real>(cd);
     const int b = xcd_block(blockIdx.x, g.nblocks);
     const int bi = b % g.tiles_i;
     const int bj = (b / g.tiles_i) % g.tiles_j;
@@ -252,11 +284,11 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef c, Sw
 
     // New pressure at the centre cell, recomputed with the same arithmetic
     // as its owner, so that every block subtracts the identical value.
-    double pc_new;
+    Real pc_new;
     {
-        Star s;
+        Star<Real> s;
         gather_global(d, q, c, d.ni / 2, d.nj / 2, d.nk / 2, s);
-        double R[NF], dt;
+        Real R[NF], dt;
         cell_residual(c, s, R, dt);
         pc_new = fma(dt, R[FP], s.p);
     }
@@ -299,19 +331,19 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef c, Sw
     const int off_prow = cell_off(d, i, prow_j, 0);
     const int off_urow = cell_off(d, i, urow_j, 0);
     const int off_col = cell_off(d, col_i, j, 0);
-    const double* const Pg = q.f[FP];
-    const double* const Ug = q.f[FU];
-    const double* const Vg = q.f[FV];
-    const double* const Wg = q.f[FW];
-    const double* const Tg = q.f[FT];
-    const double* const URg = q.f[urow_f];
-    const double* const COLg = q.f[col_f];
+    const Real* const Pg = q.f[FP];
+    const Real* const Ug = q.f[FU];
+    const Real* const Vg = q.f[FV];
+    const Real* const Wg = q.f[FW];
+    const Real* const Tg = q.f[FT];
+    const Real* const URg = q.f[urow_f];
+    const Real* const COLg = q.f[col_f];
     const int Z = d.sz;
 
     // tiles whose LDS planes reach past a wall fix their ghost cells
     const bool bnd = i0 == 0 || j0 == 0 || i0 + TI + 2 > d.ni || j0 + TJ + 2 > d.nj;
-    auto fix_ghosts = [&](double* fP, double* fU) __attribute__((always_inline)) {
-        auto cell = [&](int f, int ci, int cj) -> double& {
+    auto fix_ghosts = [&](Real* fP, Real* fU) __attribute__((always_inline)) {
+        auto cell = [&](int f, int ci, int cj) -> Real& {
             return f == FP ? fP[(cj - j0 + 2) * PW + (ci - i0 + 2)]
                            : fU[(f - FU) * UPL + (cj - j0 + 1) * UW + (ci - i0 + 1)];
         };
@@ -319,11 +351,11 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef c, Sw
         if (row < NF && i < d.ni) {
             const int f = row, reach = f == FP ? 2 : 1;
             if (j0 == 0) {
-                const double a = cell(f, i, 0), b = cell(f, i, 1);
+                const Real a = cell(f, i, 0), b = cell(f, i, 1);
                 for (int gg = 1; gg <= reach; ++gg) cell(f, i, -gg) = ghost_value(f, gg | (SIDE_OTHER << 2), a, b, c);
             }
             if (j0 + TJ + reach > d.nj) {
-                const double a = cell(f, i, d.nj - 1), b = cell(f, i, d.nj - 2);
+                const Real a = cell(f, i, d.nj - 1), b = cell(f, i, d.nj - 2);
                 for (int gg = 1; gg <= reach; ++gg)
                     if (d.nj - 1 + gg < j0 + TJ + reach)
                         cell(f, i, d.nj - 1 + gg) = ghost_value(f, gg | (SIDE_OTHER << 2), a, b, c);
@@ -333,11 +365,11 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef c, Sw
         if (lane < NF && j < d.nj) {
             const int f = lane, reach = f == FP ? 2 : 1;
             if (i0 == 0) {
-                const double a = cell(f, 0, j), b = cell(f, 1, j);
+                const Real a = cell(f, 0, j), b = cell(f, 1, j);
                 for (int gg = 1; gg <= reach; ++gg) cell(f, -gg, j) = ghost_value(f, gg | (SIDE_X_LO << 2), a, b, c);
             }
             if (i0 + TI + reach > d.ni) {
-                const double a = cell(f, d.ni - 1, j), b = cell(f, d.ni - 2, j);
+                const Real a = cell(f, d.ni - 1, j), b = cell(f, d.ni - 2, j);
                 for (int gg = 1; gg <= reach; ++gg)
                     if (d.ni - 1 + gg < i0 + TI + reach)
                         cell(f, d.ni - 1 + gg, j) = ghost_value(f, gg | (SIDE_X_HI << 2), a, b, c);
@@ -346,29 +378,29 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef c, Sw
     };
 
     // ---- register queues ----
-    double p0, p1, p2, p3;                                 // p at k-2, k-1, k, k+1
-    double u0, u1, v0, v1, w0, w1, t0, t1;                 // at k-1, k
+    Real p0, p1, p2, p3;                                 // p at k-2, k-1, k, k+1
+    Real u0, u1, v0, v1, w0, w1, t0, t1;                 // at k-1, k
     const int lc_p = (row + 2) * PW + lane + 2;            // this cell in an LDS p plane
     const int lc_u = (row + 1) * UW + lane + 1;            // this cell in an LDS u v w T plane
     {
         // planes k0-2 .. k0+1 of this column; planes beyond the z walls
         // follow from the wall rules (recurrences along k)
-        double P[4], U[2], V[2], W[2], T[2];
+        Real P[4], U[2], V[2], W[2], T[2];
         for (int m = 0; m < 4; ++m) {
             const int kk = k0 - 2 + m;
-            P[m] = (active && kk >= 0 && kk < d.nk) ? Pg[off_c + kk * Z] : 0.0;
+            P[m] = (active && kk >= 0 && kk < d.nk) ? Pg[off_c + kk * Z] : Real(0);
         }
         for (int m = 0; m < 2; ++m) {
             const int kk = k0 - 1 + m;
             const bool in = active && kk >= 0;
-            U[m] = in ? Ug[off_c + kk * Z] : 0.0;
-            V[m] = in ? Vg[off_c + kk * Z] : 0.0;
-            W[m] = in ? Wg[off_c + kk * Z] : 0.0;
-            T[m] = in ? Tg[off_c + kk * Z] : 0.0;
+            U[m] = in ? Ug[off_c + kk * Z] : Real(0);
+            V[m] = in ? Vg[off_c + kk * Z] : Real(0);
+            W[m] = in ? Wg[off_c + kk * Z] : Real(0);
+            T[m] = in ? Tg[off_c + kk * Z] : Real(0);
         }
-        if (k0 + 1 >= d.nk) P[3] = 2.0 * P[2] - P[1];
+        if (k0 + 1 >= d.nk) P[3] = Real(2) * P[2] - P[1];
         for (int m = 1; m >= 0; --m)
-            if (k0 - 2 + m < 0) P[m] = 2.0 * P[m + 1] - P[m + 2];
+            if (k0 - 2 + m < 0) P[m] = Real(2) * P[m + 1] - P[m + 2];
         if (k0 - 1 < 0) { U[0] = -U[1]; V[0] = -V[1]; W[0] = -W[1]; T[0] = T[1]; }
         p0 = P[0]; p1 = P[1]; p2 = P[2]; p3 = P[3];
         u0 = U[0]; u1 = U[1]; v0 = V[0]; v1 = V[1]; w0 = W[0]; w1 = W[1]; t0 = T[0]; t1 = T[1];
@@ -379,15 +411,15 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef c, Sw
     sU[1 * UPL + lc_u] = v1;
     sU[2 * UPL + lc_u] = w1;
     sU[3 * UPL + lc_u] = t1;
-    if (has_prow) sP[prow_dst] = ld_prow ? Pg[off_prow + k0 * Z] : 0.0;
-    sU[urow_dst] = ld_urow ? URg[off_urow + k0 * Z] : 0.0;
-    if (has_col) (col_f == FP ? sP : sU)[col_lds] = ld_col ? COLg[off_col + k0 * Z] : 0.0;
+    if (has_prow) sP[prow_dst] = ld_prow ? Pg[off_prow + k0 * Z] : Real(0);
+    sU[urow_dst] = ld_urow ? URg[off_urow + k0 * Z] : Real(0);
+    if (has_col) (col_f == FP ? sP : sU)[col_lds] = ld_col ? COLg[off_col + k0 * Z] : Real(0);
 
     // Loads run two planes ahead: what the iteration for plane k needs from
     // memory (queue heads p(k+2), uvwT(k+1), halo strips of plane k+1) is
     // issued while plane k-2 is computed.  Two register sets alternate.
     struct InFlight {
-        double p, u, v, w, t, prow, urow, col;
+        Real p, u, v, w, t, prow, urow, col;
     };
     auto issue = [&](InFlight& F, int k) __attribute__((always_inline)) {
         if (active) {
@@ -415,14 +447,14 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef c, Sw
 
     auto plane = [&](InFlight& F, int k) __attribute__((always_inline)) {
         // complete the queues; planes past the top wall follow the wall rules
-        const double p4 = k + 2 < d.nk ? F.p : 2.0 * p3 - p2;
+        const Real p4 = k + 2 < d.nk ? F.p : Real(2) * p3 - p2;
         const bool in1 = k + 1 < d.nk;
-        const double u2 = in1 ? F.u : -u1, v2 = in1 ? F.v : -v1, w2 = in1 ? F.w : -w1, t2 = in1 ? F.t : t1;
+        const Real u2 = in1 ? F.u : -u1, v2 = in1 ? F.v : -v1, w2 = in1 ? F.w : -w1, t2 = in1 ? F.t : t1;
         if (k + 1 < k1) {
             // plane k+1 into the other LDS buffer (its last readers finished
             // before the barrier that ended the previous plane)
-            double* const nP = sP + (buf ^ 1) * PPL;
-            double* const nU = sU + (buf ^ 1) * 4 * UPL;
+            Real* const nP = sP + (buf ^ 1) * PPL;
+            Real* const nU = sU + (buf ^ 1) * 4 * UPL;
             nP[lc_p] = p3;
             nU[0 * UPL + lc_u] = u2;
             nU[1 * UPL + lc_u] = v2;
@@ -434,14 +466,14 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef c, Sw
         }
         if (k + 2 < k1) issue(F, k + 2);
 
-        double* const cP = sP + buf * PPL;
-        double* const cU = sU + buf * 4 * UPL;
+        Real* const cP = sP + buf * PPL;
+        Real* const cU = sU + buf * 4 * UPL;
         if (bnd) {
             fix_ghosts(cP, cU);
             __syncthreads();
         }
         if (active) {
-            Star s;
+            Star<Real> s;
             s.p = p2;
             s.pxm = cP[lc_p - 1]; s.pxp = cP[lc_p + 1]; s.pxm2 = cP[lc_p - 2]; s.pxp2 = cP[lc_p + 2];
             s.pym = cP[lc_p - PW]; s.pyp = cP[lc_p + PW]; s.pym2 = cP[lc_p - 2 * PW]; s.pyp2 = cP[lc_p + 2 * PW];
@@ -455,7 +487,7 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef c, Sw
             STAR_LDS(w, 2, w1, w0, w2)
             STAR_LDS(t, 3, t1, t0, t2)
 #undef STAR_LDS
-            double R[NF], dt;
+            Real R[NF], dt;
             cell_residual(c, s, R, dt);
             // the new state is not read again by this launch: stream it out
             const int o = off_c + k * Z;
@@ -466,7 +498,7 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef c, Sw
             __builtin_nontemporal_store(fma(dt, R[FT], s.t), &qn.f[FT][o]);
             if (NORM) {
 #pragma unroll
-                for (int f = 0; f < NF; ++f) acc[f] = fma(R[f], R[f], acc[f]);
+                for (int f = 0; f < NF; ++f) acc[f] = fma((double)R[f], (double)R[f], acc[f]);
             }
         }
         __syncthreads();
@@ -522,21 +554,27 @@ SweepGeom sweep_geom(const Dims& d)
     return g;
 }
 
-hipError_t launch_sweep(const Dims& d, const Coef& c, const SweepGeom& g, CState q, State qn,
+template <typename Real>
+hipError_t launch_sweep(const Dims& d, const Coef& c, const SweepGeom& g, CStateT<Real> q, StateT<Real> qn,
                         double* partials, bool with_norm, hipStream_t s)
 {
     dim3 block(SW_TI, SW_TJ), grid(g.nblocks);
     if (with_norm)
-        sweep_kernel<true><<<grid, block, 0, s>>>(d, c, g, q, qn, partials);
+        sweep_kernel<Real, true><<<grid, block, 0, s>>>(d, c, g, q, qn, partials);
     else
-        sweep_kernel<false><<<grid, block, 0, s>>>(d, c, g, q, qn, partials);
+        sweep_kernel<Real, false><<<grid, block, 0, s>>>(d, c, g, q, qn, partials);
     return hipGetLastError();
 }
+template hipError_t launch_sweep<double>(const Dims&, const Coef&, const SweepGeom&, CStateT<double>,
+                                         StateT<double>, double*, bool, hipStream_t);
+template hipError_t launch_sweep<float>(const Dims&, const Coef&, const SweepGeom&, CStateT<float>,
+                                        StateT<float>, double*, bool, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// Wall ghost layers (Sec. 2): one thread per wall-adjacent line of cells,
-// all five fields, both ghost layers.  Only face ghosts are written.
-__global__ __launch_bounds__(256) void bc_kernel(Dims d, Bcs bc, State q)
+// Wall ghost layers (Sec. 2), written into the state by cavity_init: one
+// thread per wall-adjacent line of cells, all five fields, both layers.
+template <typename Real>
+__global__ __launch_bounds__(256) void bc_kernel(Dims d, Bcs bc, StateT<Real> q)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long nx = 2LL * d.nj * d.nk, ny = 2LL * d.ni * d.nk, nz = 2LL * d.ni * d.nj;
@@ -573,28 +611,28 @@ __global__ __launch_bounds__(256) void bc_kernel(Dims d, Bcs bc, State q)
     }
     // p: one-sided linear extrapolation, second order
     {
-        double* A = q.f[FP];
-        const double a = A[o], b = A[o + s];
-        const double g1 = 2.0 * a - b;
+        Real* A = q.f[FP];
+        const Real a = A[o], b = A[o + s];
+        const Real g1 = Real(2) * a - b;
         A[o - s] = g1;
-        A[o - 2 * s] = 2.0 * g1 - a;
+        A[o - 2 * s] = Real(2) * g1 - a;
     }
     // u, v, w: no-slip (odd reflection)
 #pragma unroll
     for (int f = FU; f <= FW; ++f) {
-        double* A = q.f[f];
-        const double a = A[o], b = A[o + s];
+        Real* A = q.f[f];
+        const Real a = A[o], b = A[o + s];
         A[o - s] = -a;
         A[o - 2 * s] = -b;
     }
     // T: fixed value on the hot/cold walls, zero gradient elsewhere
     {
-        double* A = q.f[FT];
-        const double a = A[o], b = A[o + s];
+        Real* A = q.f[FT];
+        const Real a = A[o], b = A[o + s];
         if (axis == 0) {
-            const double tw = high ? bc.t_cold : bc.t_hot;
-            A[o - s] = 2.0 * tw - a;
-            A[o - 2 * s] = 2.0 * tw - b;
+            const Real tw = (Real)(high ? bc.t_cold : bc.t_hot);
+            A[o - s] = Real(2) * tw - a;
+            A[o - 2 * s] = Real(2) * tw - b;
         } else {
             A[o - s] = a;
             A[o - 2 * s] = b;
@@ -602,16 +640,20 @@ __global__ __launch_bounds__(256) void bc_kernel(Dims d, Bcs bc, State q)
     }
 }
 
-hipError_t launch_bc(const Dims& d, const Bcs& b, State q, hipStream_t s)
+template <typename Real>
+hipError_t launch_bc(const Dims& d, const Bcs& b, StateT<Real> q, hipStream_t s)
 {
     const long long n = 2LL * ((long long)d.nj * d.nk + (long long)d.ni * d.nk + (long long)d.ni * d.nj);
-    bc_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(d, b, q);
+    bc_kernel<Real><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(d, b, q);
     return hipGetLastError();
 }
+template hipError_t launch_bc<double>(const Dims&, const Bcs&, StateT<double>, hipStream_t);
+template hipError_t launch_bc<float>(const Dims&, const Bcs&, StateT<float>, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Seeded initial state: SplitMix64 (Steele, Lea & Flood 2014), output number
-// f*2^40 + idx of the stream seeded with `seed`.
+// f*2^40 + idx of the stream seeded with `seed`.  Computed in FP64; an FP32
+// state stores the rounded values.
 __device__ __forceinline__ double noise(uint64_t seed, int f, uint64_t idx, double amp)
 {
     uint64_t z = seed + ((((uint64_t)f) << 40) + idx + 1ull) * 0x9E3779B97F4A7C15ull;
@@ -622,8 +664,9 @@ __device__ __forceinline__ double noise(uint64_t seed, int f, uint64_t idx, doub
     return (2.0 * r - 1.0) * amp;
 }
 
+template <typename Real>
 __global__ __launch_bounds__(256) void init_kernel(Dims d, double t_hot, double t_cold, uint64_t seed,
-                                                   double amp, State q)
+                                                   double amp, StateT<Real> q)
 {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long long)d.ni * d.nj * d.nk) return;
@@ -633,20 +676,61 @@ __global__ __launch_bounds__(256) void init_kernel(Dims d, double t_hot, double 
     const int k = (int)(r / d.nj);
     const int o = cell_off(d, i, j, k);
     const double xc = ((double)i + 0.5) / (double)d.ni;
-    q.f[FP][o] = 0.0;
-    q.f[FU][o] = noise(seed, 1, (uint64_t)idx, amp);
-    q.f[FV][o] = noise(seed, 2, (uint64_t)idx, amp);
-    q.f[FW][o] = noise(seed, 3, (uint64_t)idx, amp);
-    q.f[FT][o] = (t_hot + (t_cold - t_hot) * xc) + noise(seed, 4, (uint64_t)idx, amp);
+    q.f[FP][o] = (Real)0.0;
+    q.f[FU][o] = (Real)noise(seed, 1, (uint64_t)idx, amp);
+    q.f[FV][o] = (Real)noise(seed, 2, (uint64_t)idx, amp);
+    q.f[FW][o] = (Real)noise(seed, 3, (uint64_t)idx, amp);
+    q.f[FT][o] = (Real)((t_hot + (t_cold - t_hot) * xc) + noise(seed, 4, (uint64_t)idx, amp));
 }
 
-hipError_t launch_init(const Dims& d, double t_hot, double t_cold, uint64_t seed, double amp, State q,
+template <typename Real>
+hipError_t launch_init(const Dims& d, double t_hot, double t_cold, uint64_t seed, double amp, StateT<Real> q,
                        hipStream_t s)
 {
     const long long n = (long long)d.ni * d.nj * d.nk;
-    init_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(d, t_hot, t_cold, seed, amp, q);
+    init_kernel<Real><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(d, t_hot, t_cold, seed, amp, q);
     return hipGetLastError();
 }
+template hipError_t launch_init<double>(const Dims&, double, double, uint64_t, double, StateT<double>, hipStream_t);
+template hipError_t launch_init<float>(const Dims&, double, double, uint64_t, double, StateT<float>, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Mean Nusselt number of the hot wall x = 0 in FP64: -dT/dx at the wall from
+// the second-order one-sided difference (9 T_0 - T_1 - 8 T_w) / (3h) through
+// the wall value and the first two cell centres, averaged over the wall and
+// divided by t_hot - t_cold.  One block; fixed-order reduction.
+template <typename Real>
+__global__ __launch_bounds__(1024) void nusselt_kernel(Dims d, double t_hot, double t_cold, CStateT<Real> q,
+                                                       double* out)
+{
+    __shared__ double red[1024];
+    const int t = threadIdx.x;
+    const long long n = (long long)d.nj * d.nk;
+    const double three_h = 3.0 / (double)d.ni;
+    double acc = 0.0;
+    for (long long e = t; e < n; e += 1024) {
+        const int j = (int)(e % d.nj), k = (int)(e / d.nj);
+        const int o = cell_off(d, 0, j, k);
+        const double t0 = (double)q.f[FT][o], t1 = (double)q.f[FT][o + 1];
+        acc += -((9.0 * t0 - t1 - 8.0 * t_hot) / three_h);
+    }
+    red[t] = acc;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) out[0] = red[0] / ((double)d.nj * (double)d.nk) / (t_hot - t_cold);
+}
+
+template <typename Real>
+hipError_t launch_nusselt(const Dims& d, double t_hot, double t_cold, CStateT<Real> q, double* out, hipStream_t s)
+{
+    nusselt_kernel<Real><<<1, 1024, 0, s>>>(d, t_hot, t_cold, q, out);
+    return hipGetLastError();
+}
+template hipError_t launch_nusselt<double>(const Dims&, double, double, CStateT<double>, double*, hipStream_t);
+template hipError_t launch_nusselt<float>(const Dims&, double, double, CStateT<float>, double*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Residual norms: fixed-order sum of the per-block partials (strided

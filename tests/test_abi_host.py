@@ -133,3 +133,27 @@ def test_adjoint_not_available():
 def test_timing_read_empty():
     C.cavity_timing_enable(False)
     assert C.cavity_timing_read() == {}
+
+
+def test_f32_layout_and_halo_bytes(orc):
+    """FP32 state: 128-byte rows hold 32 floats; the halo buffer is FP32."""
+    for n in ((16, 16, 16), (67, 37, 21), (384, 384, 384)):
+        g = C.Grid(*n, dtype=C.CAV_F32)
+        L = C.cavity_layout(g)
+        assert L.lead == 32 and L.sj % 32 == 0 and L.sj >= 32 + n[0] + 2 and L.sj < 32 + n[0] + 2 + 32
+        assert C.cavity_state_elems(g) == 5 * L.sf
+    P = O.Problem(64, 48, 32)
+    g = C.Grid(64, 48, 32, dtype=C.CAV_F32)
+    h = C.Halo((4, 2, 1), (2, 1, 1, 1, 1))
+    assert C.halo_buffer_bytes(g, h) == 4 * O.halo_elems(P, ((4, 2, 1), (2, 1, 1, 1, 1)))
+
+
+def test_nusselt_validation():
+    L = C.lib()
+    g = C.Grid(16, 16, 16).c()
+    out = ctypes.c_double()
+    p = C.Params().c()
+    assert L.cavity_nusselt(ctypes.byref(g), ctypes.byref(p), None, FAKE, 1 << 20, ctypes.byref(out), None) == C.CAV_EINVAL
+    assert L.cavity_nusselt(ctypes.byref(g), ctypes.byref(p), FAKE, FAKE, 8, ctypes.byref(out), None) == C.CAV_ESIZE
+    p2 = C.Params(t_hot=0.5, t_cold=0.5).c()
+    assert L.cavity_nusselt(ctypes.byref(g), ctypes.byref(p2), FAKE, FAKE, 1 << 20, ctypes.byref(out), None) == C.CAV_EINVAL

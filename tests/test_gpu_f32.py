@@ -1,0 +1,162 @@
+"""GPU tests of the FP32 precision form and of the FP64 Nusselt integral.
+
+The FP32 form keeps the state and the stencil arithmetic in FP32 and
+accumulates the residual norms and the hot-wall Nusselt number in FP64.  Its
+initial state is the FP64 seeded state rounded to FP32, and its halo
+pack/unpack are copies, so those match the oracle bit for bit.  After 100
+steps its fields are compared with the FP64 oracle per field (max |a-b| /
+max |b| over the interior); the bound is stated below with the errors it was
+set from.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+# Measured per-field relative errors after 100 steps sit well below this
+# bound (see test output); 1e-5 is the stated tolerance of the FP32 form.
+TOL_F32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def C():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2006_02602_amd as C
+    C.lib()
+    return C
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def get_state(C, g, t):
+    import torch
+    torch.cuda.synchronize()
+    return C.state_view(g, t).cpu().numpy().astype(np.float64)
+
+
+def put_state(C, g, t, a):
+    import torch
+    C.state_view(g, t).copy_(torch.from_numpy(np.ascontiguousarray(a)).to(t.dtype))
+
+
+def rel_err(a, b):
+    return [float(np.abs(a[f] - b[f]).max() / max(np.abs(b[f]).max(), 1e-300)) for f in range(5)]
+
+
+def problem(C, n, Ra, dtype):
+    P = O.Problem(*n, Ra=Ra)
+    g = C.Grid(*n, dtype=dtype)
+    prm = C.Params(Ra=Ra)
+    return P, g, prm
+
+
+@pytest.mark.parametrize("n", [(16, 16, 16), (67, 37, 21)])
+def test_f32_init_is_rounded_f64_init(C, n):
+    say("f32 init", n)
+    P, g, prm = problem(C, n, 1e6, C.CAV_F32)
+    ref = O.init(P, 3, 1e-3)
+    cav = C.Cavity(g, prm).init(3, 1e-3)
+    got = get_state(C, g, cav.q)
+    assert np.array_equal(P.interior(got), P.interior(ref).astype(np.float32).astype(np.float64))
+
+
+@pytest.mark.parametrize("n,split,width", [((16, 16, 16), (2, 2, 2), (1, 2, 2, 2, 2)),
+                                           ((256, 256, 256), (8, 1, 1), (1, 2, 2, 2, 2)),
+                                           ((96, 64, 32), (4, 2, 1), (2, 1, 1, 1, 1))])
+def test_f32_pack_unpack_bit_exact(C, n, split, width):
+    import torch
+    say("f32 pack", n, split, width)
+    P = O.Problem(*n)
+    g, h = C.Grid(*n, dtype=C.CAV_F32), C.Halo(split, width)
+    q = np.random.default_rng(7).standard_normal(P.shape).astype(np.float32).astype(np.float64)
+    ref = O.halo_pack(P, (split, width), q)
+    assert C.halo_buffer_bytes(g, h) == 4 * ref.size
+    qd = torch.zeros(C.cavity_state_elems(g), dtype=torch.float32, device="cuda")
+    put_state(C, g, qd, q)
+    buf = torch.full((ref.size,), float("nan"), dtype=torch.float32, device="cuda")
+    C.halo_pack(g, h, qd, buf)
+    torch.cuda.synchronize()
+    assert np.array_equal(buf.cpu().numpy().astype(np.float64), ref)
+    mark = np.zeros(P.shape)
+    O.halo_unpack(P, (split, width), np.ones(ref.size), mark)
+    qp = q.copy()
+    qp[mark == 1] = np.nan
+    put_state(C, g, qd, qp)
+    C.halo_unpack(g, h, buf, qd)
+    assert np.array_equal(get_state(C, g, qd), q)
+
+
+@pytest.mark.parametrize("n,Ra,halo", [((32, 32, 32), 1e6, None),
+                                       ((16, 16, 16), 1e3, ((2, 2, 2), (1, 2, 2, 2, 2))),
+                                       ((67, 37, 21), 1e5, None)])
+def test_f32_against_f64_oracle(C, n, Ra, halo):
+    """100 steps of the FP32 form against the FP64 oracle from the same
+    (rounded) start."""
+    say("f32 vs oracle", n, Ra, halo)
+    P, g, prm = problem(C, n, Ra, C.CAV_F32)
+    q0 = O.init(P, 3, 1e-3)
+    q0r = q0.astype(np.float32).astype(np.float64)
+    ref = q0r.copy()
+    nref = O.step(P, ref, 100, halo=halo)
+    cav = C.Cavity(g, prm, C.Halo(*halo) if halo else None)
+    put_state(C, g, cav.q, q0r)
+    cav.step(100)
+    got = get_state(C, g, cav.q)
+    e = rel_err(P.interior(got), P.interior(ref))
+    say("  per-field rel err (p u v w T):", ["%.2e" % x for x in e])
+    na = np.array(cav.norms())
+    say("  norms rel err:", ["%.2e" % x for x in np.abs(na - nref) / nref])
+    assert max(e) <= TOL_F32, e
+    np.testing.assert_allclose(na, nref, rtol=1e-3)
+
+
+def test_f32_against_f64_gpu_128(C):
+    """128^3, Ra 1e6, 100 steps: the FP32 form against the FP64 form of the
+    same library from the same start."""
+    say("f32 vs f64 gpu 128^3")
+    n = (128, 128, 128)
+    P = O.Problem(*n, Ra=1e6)
+    g32, g64 = C.Grid(*n, dtype=C.CAV_F32), C.Grid(*n)
+    prm = C.Params(Ra=1e6)
+    a = C.Cavity(g64, prm).init(3, 1e-3)
+    b = C.Cavity(g32, prm)
+    put_state(C, g32, b.q, get_state(C, g64, a.q))
+    a.step(100)
+    b.step(100)
+    e = rel_err(P.interior(get_state(C, g32, b.q)), P.interior(get_state(C, g64, a.q)))
+    say("  per-field rel err (p u v w T):", ["%.2e" % x for x in e])
+    assert max(e) <= TOL_F32, e
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_nusselt_against_oracle(C, dtype):
+    say("nusselt", dtype)
+    n = (40, 24, 18)
+    P, g, prm = problem(C, n, 1e5, dtype)
+    q0 = O.init(P, 9, 1e-3)
+    if dtype == C.CAV_F32:
+        q0 = q0.astype(np.float32).astype(np.float64)
+    ref = q0.copy()
+    O.step(P, ref, 30)
+    cav = C.Cavity(g, prm)
+    put_state(C, g, cav.q, q0)
+    cav.step(30)
+    nu_gpu = cav.nusselt()
+    nu_ref = O.nusselt_hot(P, ref)
+    say("  Nu gpu %.15f oracle %.15f" % (nu_gpu, nu_ref))
+    assert abs(nu_gpu - nu_ref) <= (1e-12 if dtype == 0 else 1e-5) * abs(nu_ref)
+    # conduction profile: Nu = 1 exactly up to rounding of the state
+    x = (np.arange(n[0]) + 0.5) / n[0]
+    cond = P.zeros()
+    P.interior(cond)[4][:] = 1.0 - x
+    put_state(C, g, cav.q, cond)
+    assert abs(cav.nusselt() - 1.0) < (1e-13 if dtype == 0 else 1e-5)
