@@ -1,9 +1,11 @@
 """Benchmark: pseudo-time steps of the 256^3 FP64 cavity on one MI355X.
 
-One step = wall ghost fill + halo pack + halo unpack of the 3D (2,2,2)
-virtual split + residual/update sweep with the centre rescale (the residual
-norms are reduced on the last step), i.e. one GPU's share of an iteration
-of the paper's solver (Xue & Roy, arXiv:2006.02602, Sec. 3.1 and 4.5).
+One step = halo pack + halo unpack of the 3D (2,2,2) virtual split +
+residual/update sweep (wall ghosts derived inside it) with the centre
+rescale; the residual norms are reduced on the last step.  That is one
+GPU's share of an iteration of the paper's solver (Xue & Roy,
+arXiv:2006.02602, Sec. 3.1 and 4.5).  Also reported: halo pack/unpack per
+split and width pattern, and the FP32 precision form (384^3).
 Inputs are seeded synthetic fields already resident in HBM.  Prints ONE JSON
 line; `value` is interior grid-point updates per second.
 
@@ -85,6 +87,85 @@ def halo_bench(C, torch, grid, cav, splits, widths_list, reps):
     return out
 
 
+def f32_leg(C, torch, steps):
+    """The FP32 precision form on its own workload (384^3, Ra 1e6): FP32
+    state and stencil, FP64 norms and Nusselt; plus its per-field error
+    against the FP64 form of this library at 128^3 after 100 steps."""
+    n, Ra, seed = 384, 1e6, 3
+    g = C.Grid.cube(n, C.CAV_F32)
+    prm = C.Params(Ra=Ra)
+    cav = C.Cavity(g, prm).init(seed, 1e-3)
+    cav.step(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cav.step(steps)
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t0
+    C.cavity_timing_read()
+    C.cavity_timing_enable(True)
+    cav.step(steps)
+    torch.cuda.synchronize()
+    C.cavity_timing_enable(False)
+    kt = C.cavity_timing_read()
+    sw_n = sum(kt[k][0] for k in ("sweep", "sweep_norm") if k in kt)
+    sw_ms = sum(kt[k][1] for k in ("sweep", "sweep_norm") if k in kt) / sw_n
+    ncell = g.ncell
+    out = {"workload": "cavity384_f32_ra1e6", "steps": steps, "value": ncell * steps / t_run,
+           "unit": "grid-point updates/s", "ms_per_step": 1e3 * t_run / steps,
+           "sweep_avg_us": 1e3 * sw_ms, "sweep_GBs": 40.0 * ncell / (sw_ms * 1e-3) / 1e9,
+           "sweep_frac_hbm": 40.0 * ncell / (sw_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "residual_norms_f64": cav.norms(), "nusselt_f64": cav.nusselt()}
+    del cav
+    # accuracy: FP32 vs FP64 GPU from the same start, 128^3, 100 steps
+    m = 128
+    g64, g32 = C.Grid.cube(m), C.Grid.cube(m, C.CAV_F32)
+    a = C.Cavity(g64, prm).init(seed, 1e-3)
+    b = C.Cavity(g32, prm)
+    C.state_view(g32, b.q).copy_(C.state_view(g64, a.q).to(torch.float32))
+    a.step(100)
+    b.step(100)
+    torch.cuda.synchronize()
+    A = C.state_view(g64, a.q)[:, 2:-2, 2:-2, 2:-2]
+    B = C.state_view(g32, b.q)[:, 2:-2, 2:-2, 2:-2].to(torch.float64)
+    err = [float((B[f] - A[f]).abs().max() / A[f].abs().max()) for f in range(5)]
+    out["rel_err_vs_f64_gpu_128cubed_100steps"] = dict(zip(("p", "u", "v", "w", "T"), err))
+    out["nusselt_128cubed"] = {"f64": a.nusselt(), "f32": b.nusselt()}
+    return out
+
+
+def batch_leg(C, torch, steps):
+    """The batched form: 96 FP32 cubes of uneven edges and Rayleigh numbers,
+    k-chunk per edge and block count from the autotuner, `steps` steps
+    replayed from one HIP graph."""
+    from paper_2006_02602_amd import autotune
+    from paper_2006_02602_amd.configs import batch_workload
+    wl = batch_workload()
+    kcs = autotune.tune_kc([e for e, _, _ in wl], C.CAV_F32, cache_path="/tmp/cavity_autotune.json")
+    b = C.Batch([(C.Grid.cube(e, C.CAV_F32), C.Params(Ra=ra), kcs[e]) for e, ra, _ in wl])
+    b.init([s for _, _, s in wl])
+    nb, tb = autotune.tune_blocks(b)
+    b.init([s for _, _, s in wl])
+    torch.cuda.synchronize()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        gr = b.graph(steps, nblocks=nb, stream=st)
+        gr.launch(stream=st)
+        st.synchronize()
+        t0 = time.perf_counter()
+        gr.launch(stream=st)
+        st.synchronize()
+        dt = time.perf_counter() - t0
+        gr.destroy()
+    norms_ok = all(all(x == x and abs(x) < 1e30 for x in b.norms(m)) for m in range(len(b)))
+    return {"workload": "batch96_f32_edges24-96_ra1e3-1e6", "members": len(b), "cells": b.cells,
+            "steps": steps, "value": b.cells * steps / dt, "unit": "grid-point updates/s",
+            "ms_per_step": 1e3 * dt / steps, "launch": "one persistent kernel per step, %d steps in one HIP graph" % steps,
+            "autotuned_kc_per_edge": {str(k): v for k, v in kcs.items()}, "autotuned_blocks": nb,
+            "block_timings_ms": {str(k): v for k, v in tb.items()},
+            "bytes_per_step_algorithmic": 40 * b.cells,
+            "GBs_algorithmic": 40 * b.cells / (dt / steps) / 1e9, "norms_finite": norms_ok}
+
+
 def cpu_baseline(wl, budget_s):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     workload (same grid, parameters and halo; fewer steps)."""
@@ -113,6 +194,8 @@ def main():
     ap.add_argument("--workload", default="cavity256_f64_ra1e5")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-halo-bench", action="store_true")
+    ap.add_argument("--no-f32", action="store_true", help="skip the FP32 precision-form leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
@@ -185,6 +268,18 @@ def main():
         for r in halo_res:
             log("bench: halo", r)
 
+    f32 = None
+    if not args.no_f32:
+        log("bench: FP32 form (384^3) ...")
+        f32 = f32_leg(C, torch, 100)
+        log("bench: f32", f32)
+
+    batch = None
+    if not args.no_batch:
+        log("bench: batched form (96 cavities) ...")
+        batch = batch_leg(C, torch, 100)
+        log("bench: batch", batch)
+
     value = ncell * K / t_run
     line = {
         "metric": "grid-point updates/s + % HBM peak (stencil, pack/unpack); FP32 & batched vs FP64",
@@ -215,6 +310,18 @@ def main():
     }
     if halo_res is not None:
         line["halo"] = halo_res
+    if f32 is not None:
+        # updates/s of the FP32 sweep-only step at 384^3 against the FP64
+        # sweep rate of the headline run (both exclude the halo exchange)
+        f64_sweep_rate = ncell / (sw_ms * 1e-3)
+        f32_sweep_rate = f32["value"]
+        f32["f32_over_f64_sweep_rate"] = f32_sweep_rate / f64_sweep_rate
+        line["f32"] = f32
+    if batch is not None:
+        batch["batch_over_f64_sweep_rate"] = batch["value"] / (ncell / (sw_ms * 1e-3))
+        if f32 is not None:
+            batch["batch_over_f32_single_rate"] = batch["value"] / f32["value"]
+        line["batch"] = batch
     if not args.no_cpu:
         log("bench: CPU baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)

@@ -201,6 +201,58 @@ int cavity_adjoint_step(const cav_grid* grid, const cav_params* prm,
                         void* ws, size_t ws_bytes, double* dj_dthot,
                         double* dj_dra, hipStream_t stream);
 
+/* ---- batched form: many independent cavities, one launch per step -------
+ * A batch advances n cavities of arbitrary sizes and parameters (all of one
+ * dtype) together: every step is ONE launch of a persistent kernel whose
+ * blocks walk a device work list of (cavity, tile column, k chunk) items,
+ * each computed exactly as cavity_step computes that tile, so every
+ * member's state is bit-identical to advancing it alone with the same
+ * k-chunk length.  There is no halo exchange in the batched form. */
+typedef struct {
+    cav_grid grid;          /* member grid; dtype must match the batch      */
+    cav_params params;      /* member parameters (t_hot_field NULL)         */
+    void* q;                /* device state, cavity_state_elems(grid) elems */
+    void* q_tmp;            /* device scratch state, same size, distinct    */
+    void* ws;               /* device workspace                              */
+    size_t ws_bytes;        /* >= cavity_workspace_bytes(grid)               */
+    int32_t kc;             /* k planes per work item, 0 = whole columns    */
+} cav_batch_member;
+
+/* Host handle of a built batch (plain data; owns nothing). */
+typedef struct {
+    const void* table;      /* device table written by cavity_batch_build   */
+    int32_t members, items, dtype;
+    int32_t parity;         /* 0: newest states in q, 1: in q_tmp            */
+    uint64_t cells;         /* interior cells over all members               */
+} cav_batch;
+
+/* Bytes of the device table for these members (host array of n). */
+size_t cavity_batch_table_bytes(int32_t n, const cav_batch_member* members);
+
+/* Validate the members, write the work list and per-member descriptors into
+ * `table` (device, >= cavity_batch_table_bytes) and fill *out.  Waits for
+ * `stream` (the table is staged from host memory). */
+int cavity_batch_build(int32_t n, const cav_batch_member* members, void* table,
+                       size_t table_bytes, cav_batch* out, hipStream_t stream);
+
+/* Advance every member nsteps pseudo-time steps (same step as cavity_step
+ * without a halo): one persistent launch of `nblocks` blocks per step
+ * (0 = one per compute unit), then one norm-finalize launch for all
+ * members; each member's last-step residual norms land in its ws.  The
+ * q/q_tmp roles alternate: batch->parity tells where the newest states are
+ * (it is updated). */
+int cavity_batch_step(cav_batch* batch, int32_t nsteps, int32_t nblocks, hipStream_t stream);
+
+/* Capture nsteps (even, >= 2) batch steps on `stream` into a HIP graph and
+ * instantiate it; *graph_exec receives the executable graph, which the
+ * caller releases with cavity_batch_graph_destroy.  Each
+ * cavity_batch_graph_launch replays the nsteps steps (the parity is
+ * unchanged because nsteps is even). */
+int cavity_batch_graph_create(const cav_batch* batch, int32_t nsteps, int32_t nblocks,
+                              hipStream_t stream, void** graph_exec);
+int cavity_batch_graph_launch(void* graph_exec, hipStream_t stream);
+int cavity_batch_graph_destroy(void* graph_exec);
+
 /* Thread-local description of the last error returned on this thread. */
 const char* cavity_last_error(void);
 

@@ -15,7 +15,8 @@ from dataclasses import dataclass, field
 from typing import Optional, Sequence, Tuple
 
 from ._lib import (CAV_EHIP, CAV_EINVAL, CAV_ENONFINITE, CAV_ENOSYS, CAV_ESIZE, CAV_F32, CAV_F64, CAV_OK,
-                   EXPORTS, CavError, CavGrid, CavHalo, CavKernelTime, CavLayout, CavParams, check, lib)
+                   EXPORTS, CavBatch, CavBatchMember, CavError, CavGrid, CavHalo, CavKernelTime, CavLayout,
+                   CavParams, check, lib)
 
 NG = 2
 FIELDS = ("p", "u", "v", "w", "T")
@@ -199,6 +200,43 @@ def cavity_adjoint_step(grid, params, q_n, lam_in, lam_out, ws, dj_dthot, dj_dra
                                     _ptr(dj_dra)[0], _stream(stream)))
 
 
+def _members(members):
+    arr = (CavBatchMember * len(members))()
+    for i, m in enumerate(members):
+        arr[i] = m
+    return arr
+
+
+def cavity_batch_table_bytes(members) -> int:
+    return int(lib().cavity_batch_table_bytes(len(members), _members(members)))
+
+
+def cavity_batch_build(members, table, stream=None) -> CavBatch:
+    tp, tb = _ptr(table)
+    out = CavBatch()
+    check(lib().cavity_batch_build(len(members), _members(members), tp, tb, ctypes.byref(out), _stream(stream)))
+    return out
+
+
+def cavity_batch_step(batch: CavBatch, nsteps: int, nblocks: int = 0, stream=None) -> None:
+    check(lib().cavity_batch_step(ctypes.byref(batch), int(nsteps), int(nblocks), _stream(stream)))
+
+
+def cavity_batch_graph_create(batch: CavBatch, nsteps: int, nblocks: int = 0, stream=None):
+    h = ctypes.c_void_p()
+    check(lib().cavity_batch_graph_create(ctypes.byref(batch), int(nsteps), int(nblocks), _stream(stream),
+                                          ctypes.byref(h)))
+    return h.value
+
+
+def cavity_batch_graph_launch(graph_exec, stream=None) -> None:
+    check(lib().cavity_batch_graph_launch(graph_exec, _stream(stream)))
+
+
+def cavity_batch_graph_destroy(graph_exec) -> None:
+    check(lib().cavity_batch_graph_destroy(graph_exec))
+
+
 def cavity_last_error() -> str:
     return lib().cavity_last_error().decode(errors="replace")
 
@@ -259,5 +297,94 @@ class Cavity:
         return self.fields()[:, g:g + self.grid.nk, g:g + self.grid.nj, g:g + self.grid.ni]
 
 
-__all__ = ["Grid", "Params", "Halo", "Cavity", "CavError", "FIELDS", "NG", "EXPORTS", "state_view",
+class Batch:
+    """Many independent cavities advanced together (the batched form): one
+    persistent launch per step over all members; optional graph replay.
+
+    members: list of (Grid, Params) or (Grid, Params, kc)."""
+
+    def __init__(self, members, device: str = "cuda"):
+        import torch
+        self.grids, self.params, self.kcs = [], [], []
+        self.q, self.q_tmp, self.ws = [], [], []
+        cm = []
+        for m in members:
+            g, p = m[0], m[1]
+            kc = m[2] if len(m) > 2 else 0
+            n = cavity_state_elems(g)
+            if n == 0:
+                raise CavError(CAV_EINVAL, cavity_last_error())
+            q = torch.zeros(n, dtype=g.torch_dtype, device=device)
+            qt = torch.zeros(n, dtype=g.torch_dtype, device=device)
+            wb = cavity_workspace_bytes(g)
+            ws = torch.zeros(wb // 8, dtype=torch.float64, device=device)
+            self.grids.append(g)
+            self.params.append(p)
+            self.kcs.append(kc)
+            self.q.append(q)
+            self.q_tmp.append(qt)
+            self.ws.append(ws)
+            cm.append(CavBatchMember(g.c(), p.c(), q.data_ptr(), qt.data_ptr(), ws.data_ptr(), wb, kc))
+        self._members = cm
+        nb = cavity_batch_table_bytes(cm)
+        if nb == 0:
+            raise CavError(CAV_EINVAL, "invalid batch members")
+        self.table = torch.zeros(nb, dtype=torch.uint8, device=device)
+        self.handle = cavity_batch_build(cm, self.table)
+
+    def __len__(self):
+        return len(self.grids)
+
+    @property
+    def cells(self) -> int:
+        return int(self.handle.cells)
+
+    def init(self, seeds, noise_amp: float = 1e-3) -> "Batch":
+        """Seed every member (cavity_init on its q); the batch restarts at parity 0."""
+        for g, p, q, s in zip(self.grids, self.params, self.q, seeds):
+            cavity_init(g, p, int(s), noise_amp, q)
+        self.handle.parity = 0
+        return self
+
+    def step(self, nsteps: int, nblocks: int = 0, stream=None) -> "Batch":
+        cavity_batch_step(self.handle, nsteps, nblocks, stream)
+        return self
+
+    def state(self, m: int):
+        """Flat tensor that holds member m's newest state."""
+        return self.q_tmp[m] if self.handle.parity else self.q[m]
+
+    def fields(self, m: int):
+        return state_view(self.grids[m], self.state(m))
+
+    def norms(self, m: int):
+        return cavity_residual_norm(self.grids[m], self.ws[m])
+
+    def graph(self, nsteps: int, nblocks: int = 0, stream=None) -> "BatchGraph":
+        return BatchGraph(self, nsteps, nblocks, stream)
+
+
+class BatchGraph:
+    """An instantiated HIP graph of `nsteps` (even) batch steps."""
+
+    def __init__(self, batch: Batch, nsteps: int, nblocks: int, stream):
+        self.batch = batch
+        self.exec = cavity_batch_graph_create(batch.handle, nsteps, nblocks, stream)
+
+    def launch(self, stream=None) -> None:
+        cavity_batch_graph_launch(self.exec, stream)
+
+    def destroy(self) -> None:
+        if self.exec:
+            cavity_batch_graph_destroy(self.exec)
+            self.exec = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+__all__ = ["Batch", "BatchGraph", "Grid", "Params", "Halo", "Cavity", "CavError", "FIELDS", "NG", "EXPORTS", "state_view",
            "CAV_OK", "CAV_EINVAL", "CAV_ESIZE", "CAV_EHIP", "CAV_ENONFINITE", "CAV_ENOSYS", "CAV_F64", "CAV_F32"] + list(EXPORTS)

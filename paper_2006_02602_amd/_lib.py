@@ -25,6 +25,8 @@ ERROR_NAMES = {CAV_EINVAL: "CAV_EINVAL", CAV_ESIZE: "CAV_ESIZE", CAV_EHIP: "CAV_
 # every function include/cavity.h declares
 EXPORTS = ("cavity_layout", "cavity_state_elems", "cavity_workspace_bytes", "halo_buffer_bytes", "cavity_init",
            "cavity_step", "halo_pack", "halo_unpack", "cavity_residual_norm", "cavity_nusselt", "cavity_adjoint_step",
+           "cavity_batch_table_bytes", "cavity_batch_build", "cavity_batch_step", "cavity_batch_graph_create",
+           "cavity_batch_graph_launch", "cavity_batch_graph_destroy",
            "cavity_last_error", "cavity_timing_enable", "cavity_timing_read")
 
 
@@ -47,6 +49,16 @@ class CavHalo(ctypes.Structure):
 class CavLayout(ctypes.Structure):
     _fields_ = [("lead", ctypes.c_int64), ("sj", ctypes.c_int64), ("sk", ctypes.c_int64),
                 ("sf", ctypes.c_int64), ("origin", ctypes.c_int64)]
+
+
+class CavBatchMember(ctypes.Structure):
+    _fields_ = [("grid", CavGrid), ("params", CavParams), ("q", ctypes.c_void_p), ("q_tmp", ctypes.c_void_p),
+                ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t), ("kc", ctypes.c_int32)]
+
+
+class CavBatch(ctypes.Structure):
+    _fields_ = [("table", ctypes.c_void_p), ("members", ctypes.c_int32), ("items", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("parity", ctypes.c_int32), ("cells", ctypes.c_uint64)]
 
 
 class CavKernelTime(ctypes.Structure):
@@ -95,6 +107,19 @@ def lib():
     L.cavity_nusselt.argtypes = [G, Pp, vp, vp, sz, dp, vp]
     L.cavity_adjoint_step.restype = ctypes.c_int
     L.cavity_adjoint_step.argtypes = [G, Pp, vp, vp, vp, vp, sz, vp, vp, vp]
+    BM, BP = ctypes.POINTER(CavBatchMember), ctypes.POINTER(CavBatch)
+    L.cavity_batch_table_bytes.restype = sz
+    L.cavity_batch_table_bytes.argtypes = [i32, BM]
+    L.cavity_batch_build.restype = ctypes.c_int
+    L.cavity_batch_build.argtypes = [i32, BM, vp, sz, BP, vp]
+    L.cavity_batch_step.restype = ctypes.c_int
+    L.cavity_batch_step.argtypes = [BP, i32, i32, vp]
+    L.cavity_batch_graph_create.restype = ctypes.c_int
+    L.cavity_batch_graph_create.argtypes = [BP, i32, i32, vp, ctypes.POINTER(ctypes.c_void_p)]
+    L.cavity_batch_graph_launch.restype = ctypes.c_int
+    L.cavity_batch_graph_launch.argtypes = [vp, vp]
+    L.cavity_batch_graph_destroy.restype = ctypes.c_int
+    L.cavity_batch_graph_destroy.argtypes = [vp]
     L.cavity_last_error.restype = ctypes.c_char_p
     L.cavity_last_error.argtypes = []
     L.cavity_timing_enable.restype = ctypes.c_int

@@ -1,0 +1,89 @@
+"""Autotuner of the batched form's launch shape.
+
+The tile is one 64 x 8 column block (one wavefront per j row); what the
+batched kernel leaves open is the number of k planes per work item (kc),
+per cavity size, and the number of persistent blocks.  For each distinct
+cube edge the tuner times a small batch of that edge over the candidate kc
+values with HIP events and keeps the fastest; then it times the whole batch
+over the candidate block counts.  Results can be cached in a JSON file keyed
+by device architecture, element type and edge.
+"""
+import json
+import os
+
+import torch
+
+from . import Batch, Grid, Params
+
+KC_CANDIDATES = (4, 8, 16, 32, 0)        # 0 = whole columns (the cavity height per item)
+BLOCK_CANDIDATES = (256, 512, 768)
+
+
+def _arch():
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def _time(fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def _load(path):
+    if path and os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def _save(path, cache):
+    if path:
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+
+
+def tune_kc(edges, dtype, steps=4, reps=3, probe_members=6, cache_path=None):
+    """{edge: kc} for every distinct edge in `edges` (FP32 or FP64 cubes)."""
+    cache = _load(cache_path)
+    out = {}
+    for e in sorted(set(edges)):
+        key = "%s:dtype%d:edge%d" % (_arch(), dtype, e)
+        if key in cache:
+            out[e] = cache[key]["kc"]
+            continue
+        g = Grid.cube(e, dtype)
+        best, timings = None, {}
+        for kc in KC_CANDIDATES:
+            if kc > e:
+                continue
+            b = Batch([(g, Params(Ra=1e4), kc)] * probe_members).init(range(probe_members))
+            ms = _time(lambda: b.step(steps), reps)
+            timings[str(kc)] = ms
+            if best is None or ms < timings[str(best)]:
+                best = kc
+            del b
+        out[e] = best
+        cache[key] = {"kc": best, "ms_per_%d_steps" % steps: timings}
+    _save(cache_path, cache)
+    return out
+
+
+def tune_blocks(batch, steps=4, reps=3):
+    """Fastest persistent block count for a built batch."""
+    best, best_ms, timings = None, None, {}
+    for nb in BLOCK_CANDIDATES:
+        ms = _time(lambda: batch.step(steps, nblocks=nb), reps)
+        timings[nb] = ms
+        if best_ms is None or ms < best_ms:
+            best, best_ms = nb, ms
+    return best, timings

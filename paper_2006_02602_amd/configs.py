@@ -44,3 +44,30 @@ C0 = Workload("cavity16_f64_ra1e3", 16, 1e3, 100, 1, ((2, 2, 2),))
 C1 = Workload("cavity256_f64_ra1e5", 256, 1e5, 200, 2, ((2, 2, 2), (8, 1, 1), (4, 2, 1)))
 
 WORKLOADS = {w.name: w for w in (C0, C1)}
+
+
+# ---- batched form: 96 independent cubes of uneven sizes and Rayleigh numbers
+_MASK = (1 << 64) - 1
+BATCH_EDGES = (24, 32, 48, 64, 96)
+
+
+def splitmix64(seed: int, n: int) -> int:
+    """Output number n (0-based) of the SplitMix64 stream seeded with `seed`
+    (Steele, Lea & Flood 2014)."""
+    z = (seed + (n + 1) * 0x9E3779B97F4A7C15) & _MASK
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK
+    return z ^ (z >> 31)
+
+
+def batch_workload(count: int = 96, seed: int = 4):
+    """[(edge, Ra, init_seed)] of the batched workload: cube edges drawn
+    uniformly from BATCH_EDGES and log10(Ra) uniformly from [3, 6] with
+    SplitMix64(seed) outputs 2c and 2c+1 for cavity c; every cavity is seeded
+    like the small parity case (noise 1e-3, T linear in x)."""
+    out = []
+    for c in range(count):
+        edge = BATCH_EDGES[splitmix64(seed, 2 * c) % len(BATCH_EDGES)]
+        r = (splitmix64(seed, 2 * c + 1) >> 11) * 2.0 ** -53
+        out.append((edge, 10.0 ** (3.0 + 3.0 * r), seed * 1000 + c))
+    return out

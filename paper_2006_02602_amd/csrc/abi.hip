@@ -4,6 +4,7 @@
 #include "cavity.h"
 #include "cavity_internal.h"
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -207,10 +208,91 @@ size_t halo_elems(const HaloGeom& h)
 
 constexpr size_t WS_HEAD = 64;   // 5 final norms, padded
 
+// Sweep blocks resident at once: one per compute unit (the sweep needs
+// more than 128 VGPRs per lane, so one 8-wave block fills a CU).  Queried
+// once; 256 (MI355X) when no device is visible.
+int device_slots()
+{
+    static int slots = 0;
+    if (slots == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        slots = cus;
+    }
+    return slots;
+}
+
+// Large enough for any k-chunk length (one partial per tile and plane).
 size_t ws_bytes_of(const Dims& d)
 {
-    const SweepGeom g = sweep_geom(d);
-    return WS_HEAD + (size_t)g.nblocks * NF * sizeof(double);
+    const size_t tiles = (size_t)((d.ni + SW_TI - 1) / SW_TI) * ((d.nj + SW_TJ - 1) / SW_TJ);
+    return WS_HEAD + tiles * d.nk * NF * sizeof(double);
+}
+
+// Work items of a batch member for k-chunk length kc (0 = whole columns).
+SweepGeom member_geom(const Dims& d, int kc)
+{
+    SweepGeom g;
+    g.tiles_i = (d.ni + SW_TI - 1) / SW_TI;
+    g.tiles_j = (d.nj + SW_TJ - 1) / SW_TJ;
+    g.kc = (kc > 0 && kc < d.nk) ? kc : d.nk;
+    g.nkc = (d.nk + g.kc - 1) / g.kc;
+    g.nblocks = g.tiles_i * g.tiles_j * g.nkc;
+    return g;
+}
+
+int check_member(const cav_batch_member& m, int idx, int dtype)
+{
+    int rc;
+    if ((rc = check_grid(&m.grid)) || (rc = check_params(&m.params)))
+        return fail(rc, "batch member %d: %s", idx, std::string(g_err).c_str());
+    if (m.grid.dtype != dtype) return fail(CAV_EINVAL, "batch member %d: dtype differs from member 0", idx);
+    if (!m.q || !m.q_tmp || !m.ws) return fail(CAV_EINVAL, "batch member %d: q, q_tmp and ws must not be NULL", idx);
+    if (m.q == m.q_tmp) return fail(CAV_EINVAL, "batch member %d: q and q_tmp must be distinct", idx);
+    if (m.kc < 0) return fail(CAV_EINVAL, "batch member %d: kc = %d must be >= 0", idx, m.kc);
+    const size_t need = ws_bytes_of(dims_of(&m.grid));
+    if (m.ws_bytes < need) return fail(CAV_ESIZE, "batch member %d: ws_bytes %zu < required %zu", idx, m.ws_bytes, need);
+    return CAV_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <typename Real>
+hipError_t batch_launches(const cav_batch& b, int32_t nsteps, int nblocks, int parity, hipStream_t stream, bool timed)
+{
+    const BatchCav* cavs = static_cast<const BatchCav*>(b.table);
+    const BatchItem* items = reinterpret_cast<const BatchItem*>(static_cast<const char*>(b.table) +
+                                                                align256(sizeof(BatchCav) * b.members));
+    hipError_t e = hipSuccess;
+    for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
+        const bool last = n == nsteps - 1;
+        auto go = [&] { return launch_batch<Real>(cavs, items, b.items, parity, last, nblocks, stream); };
+        e = timed ? run(last ? "batch_norm" : "batch", stream, go) : go();
+        parity ^= 1;
+    }
+    if (e == hipSuccess && nsteps > 0) {
+        auto fin = [&] { return launch_batch_norms(cavs, b.members, stream); };
+        e = timed ? run("batch_norm_finalize", stream, fin) : fin();
+    }
+    return e;
+}
+
+int check_batch(const cav_batch* b)
+{
+    if (!b || !b->table) return fail(CAV_EINVAL, "batch (or its table) is NULL");
+    if (b->members < 1 || b->items < 1) return fail(CAV_EINVAL, "empty batch");
+    if (b->dtype != CAV_F64 && b->dtype != CAV_F32) return fail(CAV_EINVAL, "unknown batch dtype %d", b->dtype);
+    if (b->parity != 0 && b->parity != 1) return fail(CAV_EINVAL, "batch parity must be 0 or 1");
+    return CAV_OK;
+}
+
+int default_blocks()
+{
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return cus > 0 ? cus : 256;
 }
 
 int do_halo(const cav_grid* grid, const HaloGeom& hg, void* q, void* buf, bool pack, hipStream_t s)
@@ -233,7 +315,7 @@ int step_impl(const cav_grid* grid, const cav_params* prm, const cav_halo* halo,
     int rc;
     const Dims d = dims_of(grid);
     const Coef c = coef_of(grid, prm);
-    const SweepGeom g = sweep_geom(d);
+    const SweepGeom g = sweep_geom(d, device_slots());
     double* wsd = static_cast<double*>(ws);
     double* partials = reinterpret_cast<double*>(static_cast<char*>(ws) + WS_HEAD);
     void* cur = q;
@@ -418,6 +500,131 @@ int cavity_adjoint_step(const cav_grid*, const cav_params*, const void*, const v
                         double*, double*, hipStream_t)
 {
     return fail(CAV_ENOSYS, "cavity_adjoint_step is not available in this build");
+}
+
+size_t cavity_batch_table_bytes(int32_t n, const cav_batch_member* members)
+{
+    if (n < 1 || !members) return 0;
+    size_t items = 0;
+    for (int m = 0; m < n; ++m) {
+        if (check_grid(&members[m].grid) != CAV_OK || members[m].kc < 0) return 0;
+        items += (size_t)member_geom(dims_of(&members[m].grid), members[m].kc).nblocks;
+    }
+    return align256(sizeof(BatchCav) * n) + sizeof(BatchItem) * items;
+}
+
+int cavity_batch_build(int32_t n, const cav_batch_member* members, void* table, size_t table_bytes, cav_batch* out,
+                       hipStream_t stream)
+{
+    int rc;
+    if (n < 1 || !members || !table || !out) return fail(CAV_EINVAL, "n >= 1, members, table and out are required");
+    const int dtype = members[0].grid.dtype;
+    for (int m = 0; m < n; ++m)
+        if ((rc = check_member(members[m], m, dtype))) return rc;
+    const size_t need = cavity_batch_table_bytes(n, members);
+    if (table_bytes < need) return fail(CAV_ESIZE, "table_bytes %zu < required %zu", table_bytes, need);
+
+    std::vector<BatchCav> cavs(n);
+    struct Work { BatchItem it; long long cost; };
+    std::vector<Work> work;
+    uint64_t cells = 0;
+    for (int m = 0; m < n; ++m) {
+        const cav_batch_member& mb = members[m];
+        const Dims d = dims_of(&mb.grid);
+        const SweepGeom g = member_geom(d, mb.kc);
+        BatchCav& cv = cavs[m];
+        cv.d = d;
+        cv.tiles_i = g.tiles_i;
+        cv.tiles_j = g.tiles_j;
+        cv.kc = g.kc;
+        cv.ntiles = g.nblocks;
+        cv.c = coef_of(&mb.grid, &mb.params);
+        cv.q = mb.q;
+        cv.q_tmp = mb.q_tmp;
+        cv.ws = static_cast<double*>(mb.ws);
+        cv.fstride = (long long)field_elems(d);
+        cells += (uint64_t)d.ni * d.nj * d.nk;
+        for (int t = 0; t < g.nblocks; ++t) {
+            const int bi = t % g.tiles_i, bj = (t / g.tiles_i) % g.tiles_j, bk = t / (g.tiles_i * g.tiles_j);
+            const long long ci = std::min(SW_TI, d.ni - bi * SW_TI), cj = std::min(SW_TJ, d.nj - bj * SW_TJ);
+            const long long ck = std::min(g.kc, d.nk - bk * g.kc);
+            work.push_back({{m, t}, ci * cj * ck});
+        }
+    }
+    // longest items first, so the persistent blocks finish together
+    std::stable_sort(work.begin(), work.end(), [](const Work& a, const Work& b) { return a.cost > b.cost; });
+    std::vector<char> host(need, 0);
+    std::memcpy(host.data(), cavs.data(), sizeof(BatchCav) * n);
+    BatchItem* items = reinterpret_cast<BatchItem*>(host.data() + align256(sizeof(BatchCav) * n));
+    for (size_t w = 0; w < work.size(); ++w) items[w] = work[w].it;
+    hipError_t e = hipMemcpyAsync(table, host.data(), need, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail("batch table upload", e);
+    out->table = table;
+    out->members = n;
+    out->items = (int32_t)work.size();
+    out->dtype = dtype;
+    out->parity = 0;
+    out->cells = cells;
+    return CAV_OK;
+}
+
+int cavity_batch_step(cav_batch* batch, int32_t nsteps, int32_t nblocks, hipStream_t stream)
+{
+    int rc;
+    if ((rc = check_batch(batch))) return rc;
+    if (nsteps < 0) return fail(CAV_EINVAL, "nsteps = %d must be >= 0", nsteps);
+    if (nblocks < 0) return fail(CAV_EINVAL, "nblocks = %d must be >= 0", nblocks);
+    if (nsteps == 0) return CAV_OK;
+    const int nb = nblocks ? nblocks : default_blocks();
+    const hipError_t e = batch->dtype == CAV_F32 ? batch_launches<float>(*batch, nsteps, nb, batch->parity, stream, true)
+                                                 : batch_launches<double>(*batch, nsteps, nb, batch->parity, stream, true);
+    if (e != hipSuccess) return hip_fail("batch launch", e);
+    batch->parity ^= (nsteps & 1);
+    return CAV_OK;
+}
+
+int cavity_batch_graph_create(const cav_batch* batch, int32_t nsteps, int32_t nblocks, hipStream_t stream,
+                              void** graph_exec)
+{
+    int rc;
+    if ((rc = check_batch(batch))) return rc;
+    if (nsteps < 2 || (nsteps & 1)) return fail(CAV_EINVAL, "nsteps = %d must be even and >= 2", nsteps);
+    if (nblocks < 0) return fail(CAV_EINVAL, "nblocks = %d must be >= 0", nblocks);
+    if (!graph_exec) return fail(CAV_EINVAL, "graph_exec is NULL");
+    if (!stream) return fail(CAV_EINVAL, "graph capture needs a created stream, not the null stream");
+    const int nb = nblocks ? nblocks : default_blocks();
+    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail("begin capture", e);
+    hipError_t el = batch->dtype == CAV_F32 ? batch_launches<float>(*batch, nsteps, nb, batch->parity, stream, false)
+                                            : batch_launches<double>(*batch, nsteps, nb, batch->parity, stream, false);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(stream, &graph);
+    if (el != hipSuccess || e != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        return hip_fail("batch capture", el != hipSuccess ? el : e);
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail("graph instantiate", e);
+    *graph_exec = exec;
+    return CAV_OK;
+}
+
+int cavity_batch_graph_launch(void* graph_exec, hipStream_t stream)
+{
+    if (!graph_exec) return fail(CAV_EINVAL, "graph_exec is NULL");
+    const hipError_t e = run("batch_graph", stream,
+                             [&] { return hipGraphLaunch(static_cast<hipGraphExec_t>(graph_exec), stream); });
+    return e == hipSuccess ? CAV_OK : hip_fail("graph launch", e);
+}
+
+int cavity_batch_graph_destroy(void* graph_exec)
+{
+    if (!graph_exec) return CAV_OK;
+    const hipError_t e = hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph_exec));
+    return e == hipSuccess ? CAV_OK : hip_fail("graph destroy", e);
 }
 
 const char* cavity_last_error(void) { return g_err; }

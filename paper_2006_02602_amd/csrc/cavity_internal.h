@@ -65,7 +65,7 @@ struct SweepGeom {
     int nkc;                  // k chunks
     int nblocks;              // tiles_i * tiles_j * nkc
 };
-SweepGeom sweep_geom(const Dims& d);
+SweepGeom sweep_geom(const Dims& d, int slots);     // slots: blocks resident at once
 
 struct Bcs {
     double t_hot, t_cold;
@@ -82,6 +82,21 @@ struct HaloGeom {
     int face_blocks;          // blocks per (subdomain, face)
 };
 
+// One member of a batch and one work item (a tile column's k chunk).
+struct BatchCav {
+    Dims d;
+    int tiles_i, tiles_j, kc, ntiles;     // ntiles = tiles_i * tiles_j * (k chunks)
+    Coef c;
+    void* q;                              // state, q_tmp the scratch state
+    void* q_tmp;
+    double* ws;                           // workspace (norms, then partials)
+    long long fstride;                    // elements per field
+};
+struct BatchItem {
+    int cav, tile;
+};
+constexpr int WS_HEAD_DOUBLES = 8;        // norms (5), Nusselt, padding
+
 // Launchers (return hipGetLastError() of the launch); Real = double or float.
 template <typename Real>
 hipError_t launch_bc(const Dims& d, const Bcs& b, StateT<Real> q, hipStream_t s);
@@ -96,6 +111,10 @@ hipError_t launch_norm_finalize(const double* partials, int nblocks, double ncel
 template <typename Real>
 hipError_t launch_halo(const Dims& d, const HaloGeom& h, StateT<Real> q, Real* buf, bool pack,
                        hipStream_t s);
+template <typename Real>
+hipError_t launch_batch(const BatchCav* cavs, const BatchItem* items, int nitems, int parity, bool with_norm,
+                        int nblocks, hipStream_t s);
+hipError_t launch_batch_norms(const BatchCav* cavs, int members, hipStream_t s);
 template <typename Real>
 hipError_t launch_nusselt(const Dims& d, double t_hot, double t_cold, CStateT<Real> q, double* out,
                           hipStream_t s);

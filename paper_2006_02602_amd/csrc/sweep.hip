@@ -257,26 +257,39 @@ __device__ __forceinline__ int xcd_block(int bid, int nb)
 // written into one buffer while plane k is computed from the other, so each
 // plane costs one barrier; global loads run two planes ahead.
 // Wall ghosts are derived while loading (Slot), never read from HBM.
+// LDS of one sweep block: two double-buffered planes of p (halo 2) and of
+// u, v, w, T (halo 1).
+template <typename Real>
+struct SweepLds {
+    static constexpr int TI = SW_TI, TJ = SW_TJ;
+    static constexpr int PW = TI + 4;              // row pitch, p
+    static constexpr int UW = TI + 2;              // row pitch, u v w T
+    static constexpr int PPL = (TJ + 4) * PW;      // plane, p
+    static constexpr int UPL = (TJ + 2) * UW;      // plane, one of u v w T
+    Real p[2 * PPL];
+    Real u[2 * 4 * UPL];
+    double red[TJ][NF];
+};
+
+// One tile: columns [i0, i0+64) x [j0, j0+8) of logical tile b, planes of
+// its k chunk.  Used by the single-cavity sweep and by the batched kernel.
 template <typename Real, bool NORM>
-__global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef cd, SweepGeom g, CStateT<Real> q,
-                                                              StateT<Real> qn, double* partials)
+__device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, int tiles_i, int tiles_j, int kc,
+                                           int b, const CStateT<Real>& q, const StateT<Real>& qn,
+                                           double* partials, SweepLds<Real>& L)
 {
     constexpr int TI = SW_TI, TJ = SW_TJ;
-    constexpr int PW = TI + 4;              // LDS row pitch, p
-    constexpr int UW = TI + 2;              // LDS row pitch, u v w T
-    constexpr int PPL = (TJ + 4) * PW;      // LDS plane, p
-    constexpr int UPL = (TJ + 2) * UW;      // LDS plane, one of u v w T
-    __shared__ Real sP[2 * PPL];
-    __shared__ Real sU[2 * 4 * UPL];
+    constexpr int PW = SweepLds<Real>::PW, UW = SweepLds<Real>::UW;
+    constexpr int PPL = SweepLds<Real>::PPL, UPL = SweepLds<Real>::UPL;
+    Real* const sP = L.p;
+    Real* const sU = L.u;
 
-    const CoefR<Real> c = coef_as<Real>(cd);
-    const int b = xcd_block(blockIdx.x, g.nblocks);
-    const int bi = b % g.tiles_i;
-    const int bj = (b / g.tiles_i) % g.tiles_j;
-    const int bk = b / (g.tiles_i * g.tiles_j);
+    const int bi = b % tiles_i;
+    const int bj = (b / tiles_i) % tiles_j;
+    const int bk = b / (tiles_i * tiles_j);
     const int i0 = bi * TI, j0 = bj * TJ;
-    const int k0 = bk * g.kc;
-    const int k1 = min(k0 + g.kc, d.nk);
+    const int k0 = bk * kc;
+    const int k1 = min(k0 + kc, d.nk);
 
     const int lane = threadIdx.x, row = threadIdx.y;
     const int i = i0 + lane, j = j0 + row;
@@ -515,7 +528,7 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef cd, S
     if (NORM) {
         // fixed-order block reduction: butterfly within the wavefront, then
         // the 8 wavefront sums in order
-        __shared__ double red[TJ][NF];
+        auto& red = L.red;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             double v = acc[f];
@@ -537,18 +550,40 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef cd, S
     }
 }
 
-SweepGeom sweep_geom(const Dims& d)
+template <typename Real, bool NORM>
+__global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef cd, SweepGeom g, CStateT<Real> q,
+                                                              StateT<Real> qn, double* partials)
+{
+    __shared__ SweepLds<Real> L;
+    const CoefR<Real> c = coef_as<Real>(cd);
+    sweep_tile<Real, NORM>(d, c, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks), q, qn, partials, L);
+}
+
+SweepGeom sweep_geom(const Dims& d, int slots)
 {
     SweepGeom g;
     g.tiles_i = (d.ni + SW_TI - 1) / SW_TI;
     g.tiles_j = (d.nj + SW_TJ - 1) / SW_TJ;
     const int tiles = g.tiles_i * g.tiles_j;
-    // aim at one round of ~256 blocks (one 8-wave block per CU: the sweep
-    // needs more than 128 VGPRs) with at least 8 planes each
-    const int target = 256;
-    int nkc = (target + tiles - 1) / tiles;
-    nkc = max(1, min(nkc, (d.nk + 7) / 8));
-    g.kc = (d.nk + nkc - 1) / nkc;
+    // Split the k columns into nkc chunks so that the launch finishes
+    // earliest: blocks run in rounds of `slots` (one resident block per
+    // compute unit), a block costs its planes plus ~3 planes of start-up
+    // (the queue and halo planes it loads before its first plane).
+    const int overhead = 3;
+    long long best_cost = -1;
+    int best = 1;
+    const int max_nkc = max(1, d.nk / 4);
+    for (int nkc = 1; nkc <= max_nkc; ++nkc) {
+        const int kc = (d.nk + nkc - 1) / nkc;
+        const long long blocks = (long long)tiles * ((d.nk + kc - 1) / kc);
+        const long long rounds = (blocks + slots - 1) / slots;
+        const long long cost = rounds * (kc + overhead);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = nkc;
+        }
+    }
+    g.kc = (d.nk + best - 1) / best;
     g.nkc = (d.nk + g.kc - 1) / g.kc;
     g.nblocks = tiles * g.nkc;
     return g;
@@ -569,6 +604,79 @@ template hipError_t launch_sweep<double>(const Dims&, const Coef&, const SweepGe
                                          StateT<double>, double*, bool, hipStream_t);
 template hipError_t launch_sweep<float>(const Dims&, const Coef&, const SweepGeom&, CStateT<float>,
                                         StateT<float>, double*, bool, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Batched form: a persistent grid walks the work list of all members; each
+// item is one tile column's k chunk of one member, computed by the same
+// sweep_tile as the single-cavity sweep.  `parity` selects which of q and
+// q_tmp holds the current state of every member.
+template <typename Real, bool NORM>
+__global__ __launch_bounds__(SW_TI * SW_TJ) void batch_kernel(const BatchCav* __restrict__ cavs,
+                                                              const BatchItem* __restrict__ items, int nitems,
+                                                              int parity)
+{
+    __shared__ SweepLds<Real> L;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BatchItem w = items[it];
+        const BatchCav& cv = cavs[w.cav];
+        const Dims d = cv.d;
+        const CoefR<Real> c = coef_as<Real>(cv.c);
+        const Real* cur = static_cast<const Real*>(parity ? cv.q_tmp : cv.q);
+        Real* nxt = static_cast<Real*>(parity ? cv.q : cv.q_tmp);
+        CStateT<Real> qs;
+        StateT<Real> qn;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            qs.f[f] = cur + f * cv.fstride;
+            qn.f[f] = nxt + f * cv.fstride;
+        }
+        sweep_tile<Real, NORM>(d, c, cv.tiles_i, cv.tiles_j, cv.kc, w.tile, qs, qn, cv.ws + WS_HEAD_DOUBLES, L);
+        __syncthreads();                  // LDS is reused by the next item
+    }
+}
+
+template <typename Real>
+hipError_t launch_batch(const BatchCav* cavs, const BatchItem* items, int nitems, int parity, bool with_norm,
+                        int nblocks, hipStream_t s)
+{
+    dim3 block(SW_TI, SW_TJ), grid(nblocks);
+    if (with_norm)
+        batch_kernel<Real, true><<<grid, block, 0, s>>>(cavs, items, nitems, parity);
+    else
+        batch_kernel<Real, false><<<grid, block, 0, s>>>(cavs, items, nitems, parity);
+    return hipGetLastError();
+}
+template hipError_t launch_batch<double>(const BatchCav*, const BatchItem*, int, int, bool, int, hipStream_t);
+template hipError_t launch_batch<float>(const BatchCav*, const BatchItem*, int, int, bool, int, hipStream_t);
+
+// Residual norms of every member: one block per member, the same
+// fixed-order reduction as the single-cavity finalize.
+__global__ __launch_bounds__(256) void batch_norm_kernel(const BatchCav* __restrict__ cavs)
+{
+    __shared__ double red[NF][256];
+    const BatchCav& cv = cavs[blockIdx.x];
+    const double* part = cv.ws + WS_HEAD_DOUBLES;
+    const int t = threadIdx.x;
+    for (int f = 0; f < NF; ++f) {
+        double s = 0.0;
+        for (int b = t; b < cv.ntiles; b += 256) s += part[(size_t)b * NF + f];
+        red[f][t] = s;
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int f = 0; f < NF; ++f) red[f][t] += red[f][t + w];
+        __syncthreads();
+    }
+    const double ncell = (double)cv.d.ni * cv.d.nj * cv.d.nk;
+    if (t < NF) cv.ws[t] = sqrt(red[t][0] / ncell);
+}
+
+hipError_t launch_batch_norms(const BatchCav* cavs, int members, hipStream_t s)
+{
+    batch_norm_kernel<<<members, 256, 0, s>>>(cavs);
+    return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // Wall ghost layers (Sec. 2), written into the state by cavity_init: one

@@ -157,3 +157,44 @@ def test_nusselt_validation():
     assert L.cavity_nusselt(ctypes.byref(g), ctypes.byref(p), FAKE, FAKE, 8, ctypes.byref(out), None) == C.CAV_ESIZE
     p2 = C.Params(t_hot=0.5, t_cold=0.5).c()
     assert L.cavity_nusselt(ctypes.byref(g), ctypes.byref(p2), FAKE, FAKE, 1 << 20, ctypes.byref(out), None) == C.CAV_EINVAL
+
+
+def _member(n=(16, 16, 16), dtype=0, q=0x1000, qt=0x2000, ws=0x3000, wsb=1 << 30, kc=0):
+    return _lib.CavBatchMember(C.Grid(*n, dtype=dtype).c(), C.Params().c(), q, qt, ws, wsb, kc)
+
+
+def test_batch_validation():
+    """Batch build/step/graph reject bad input before touching the GPU."""
+    L = C.lib()
+    ok = [_member(), _member((24, 20, 9))]
+    assert C.cavity_batch_table_bytes(ok) > 0
+    assert C.cavity_batch_table_bytes([_member((1, 4, 4))]) == 0
+    out = _lib.CavBatch()
+
+    def build(ms, tb=1 << 20):
+        arr = (_lib.CavBatchMember * len(ms))(*ms)
+        return L.cavity_batch_build(len(ms), arr, FAKE, tb, ctypes.byref(out), None)
+
+    assert build([_member(), _member(dtype=1)]) == C.CAV_EINVAL          # mixed dtypes
+    assert build([_member(wsb=8)]) == C.CAV_ESIZE                        # workspace too small
+    assert build([_member(q=0x5000, qt=0x5000)]) == C.CAV_EINVAL         # q == q_tmp
+    assert build([_member(kc=-1)]) == C.CAV_EINVAL
+    assert build(ok, tb=16) == C.CAV_ESIZE                               # table too small
+    bad = _lib.CavBatch(None, 1, 1, 0, 0, 1)
+    assert L.cavity_batch_step(ctypes.byref(bad), 1, 0, None) == C.CAV_EINVAL
+    fake = _lib.CavBatch(0x1000, 1, 1, 0, 0, 1)
+    h = ctypes.c_void_p()
+    assert L.cavity_batch_step(ctypes.byref(fake), -1, 0, None) == C.CAV_EINVAL
+    assert L.cavity_batch_graph_create(ctypes.byref(fake), 3, 0, FAKE, ctypes.byref(h)) == C.CAV_EINVAL
+    assert L.cavity_batch_graph_create(ctypes.byref(fake), 2, 0, None, ctypes.byref(h)) == C.CAV_EINVAL
+    assert L.cavity_batch_graph_launch(None, None) == C.CAV_EINVAL
+
+
+def test_batch_workload_recipe():
+    from paper_2006_02602_amd.configs import BATCH_EDGES, batch_workload, splitmix64
+    assert splitmix64(0, 0) == 0xE220A8397B1DCDAF
+    w = batch_workload()
+    assert len(w) == 96 and len({s for _, _, s in w}) == 96
+    assert {e for e, _, _ in w} == set(BATCH_EDGES)
+    assert all(1e3 <= ra < 1e6 for _, ra, _ in w)
+    assert w == batch_workload()

@@ -1,0 +1,128 @@
+"""GPU tests of the batched form: many cavities advanced by one persistent
+launch per step, optionally replayed from a HIP graph.
+
+Every member must come out bit-identical to advancing it alone with
+cavity_step (the batched kernel runs the same per-tile code), whatever the
+k-chunk length of its work items; graph replays must equal eager steps.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+MEMBERS = [((16, 16, 16), 1e3), ((67, 37, 21), 1e5), ((24, 24, 24), 3e4), ((40, 9, 13), 1e6),
+           ((96, 96, 96), 2e5), ((5, 70, 11), 1e4)]
+
+
+@pytest.fixture(scope="module")
+def C():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2006_02602_amd as C
+    C.lib()
+    return C
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def interior(C, g, t):
+    import torch
+    torch.cuda.synchronize()
+    v = C.state_view(g, t)
+    return v[:, 2:-2, 2:-2, 2:-2].cpu().numpy()
+
+
+def build(C, dtype, kc=0):
+    return C.Batch([(C.Grid(*n, dtype=dtype), C.Params(Ra=Ra), kc) for n, Ra in MEMBERS])
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("nsteps", [6, 7])
+def test_batch_matches_single_cavities(C, dtype, nsteps):
+    say("batch vs single", dtype, nsteps)
+    b = build(C, dtype).init(range(100, 100 + len(MEMBERS)))
+    b.step(nsteps)
+    for m, (n, Ra) in enumerate(MEMBERS):
+        g = C.Grid(*n, dtype=dtype)
+        cav = C.Cavity(g, C.Params(Ra=Ra)).init(100 + m)
+        cav.step(nsteps)
+        assert np.array_equal(interior(C, g, b.state(m)), interior(C, g, cav.q)), (m, n)
+        # the norms' partial sums are grouped by work item, so they agree to rounding
+        np.testing.assert_allclose(b.norms(m), cav.norms(), rtol=1e-12)
+
+
+def test_batch_result_is_independent_of_k_chunks(C):
+    """Per-cell arithmetic does not depend on how the k columns are cut into
+    work items: states bit-identical, norms (summed in another grouping)
+    equal to rounding."""
+    say("batch kc invariance")
+    a = build(C, 0).init(range(len(MEMBERS)))
+    b = build(C, 0, kc=3).init(range(len(MEMBERS)))
+    a.step(5)
+    b.step(5)
+    for m, (n, _) in enumerate(MEMBERS):
+        g = C.Grid(*n)
+        assert np.array_equal(interior(C, g, a.state(m)), interior(C, g, b.state(m)))
+        np.testing.assert_allclose(b.norms(m), a.norms(m), rtol=1e-13)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_graph_replays_equal_eager_steps(C, dtype):
+    import torch
+    say("batch graph", dtype)
+    s = torch.cuda.Stream()
+    eager = build(C, dtype).init(range(7, 7 + len(MEMBERS)))
+    graphed = build(C, dtype).init(range(7, 7 + len(MEMBERS)))
+    eager.step(6)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        gr = graphed.graph(2, stream=s)
+        for r in range(3):
+            gr.launch(stream=s)
+            s.synchronize()
+            _ = torch.ones(1000, device="cuda").sum().item()      # eager work between replays
+        gr.destroy()
+    torch.cuda.synchronize()
+    for m, (n, _) in enumerate(MEMBERS):
+        g = C.Grid(*n, dtype=dtype)
+        assert np.array_equal(interior(C, g, eager.state(m)), interior(C, g, graphed.state(m))), m
+        assert eager.norms(m) == graphed.norms(m)
+
+
+def test_batch_member_against_oracle(C):
+    """One member of a mixed batch against the FP64 oracle (1e-12)."""
+    say("batch vs oracle")
+    b = C.Batch([(C.Grid(*n), C.Params(Ra=Ra)) for n, Ra in MEMBERS[:4]])
+    P = O.Problem(*MEMBERS[1][0], Ra=MEMBERS[1][1])
+    q0 = O.init(P, 42, 1e-3)
+    b.init(range(4))
+    import torch
+    C.state_view(b.grids[1], b.q[1]).copy_(torch.from_numpy(q0))
+    b.step(10)
+    ref = q0.copy()
+    O.step(P, ref, 10)
+    got = interior(C, b.grids[1], b.state(1))
+    want = P.interior(ref)
+    err = max(float(np.abs(got[f] - want[f]).max() / np.abs(want[f]).max()) for f in range(5))
+    say("  rel err", err)
+    assert err <= 1e-12
+
+
+def test_autotuner_returns_valid_choices(C):
+    from paper_2006_02602_amd import autotune
+    say("autotune")
+    kcs = autotune.tune_kc([24, 32], dtype=1, steps=2, reps=1, probe_members=2)
+    assert set(kcs) == {24, 32}
+    for e, kc in kcs.items():
+        assert kc in autotune.KC_CANDIDATES and kc <= e
+    b = C.Batch([(C.Grid.cube(e, 1), C.Params(), kcs[e]) for e in (24, 32, 32)]).init([1, 2, 3])
+    nb, t = autotune.tune_blocks(b, steps=2, reps=1)
+    assert nb in autotune.BLOCK_CANDIDATES and len(t) == len(autotune.BLOCK_CANDIDATES)
