@@ -56,7 +56,7 @@ extern "C" {
 #define CAV_ESIZE     (-2)  /* a caller buffer is smaller than required        */
 #define CAV_EHIP      (-3)  /* a HIP launch or runtime call failed             */
 #define CAV_ENONFINITE (-4) /* a residual norm is NaN or infinite              */
-#define CAV_ENOSYS    (-5)  /* operation not available in this build           */
+#define CAV_ENOSYS    (-5)  /* operation not available (reserved)              */
 
 /* ---- element types ---------------------------------------------------- */
 #define CAV_F64 0   /* state and stencil arithmetic in FP64                  */
@@ -78,7 +78,14 @@ typedef struct {
  *   cfl    pseudo-time CFL number of the local time step
  *   eps4   coefficient of the fourth-difference pressure dissipation (Eq. 1)
  *   kappa, u_ref   artificial compressibility: beta^2 = max(|V|^2, kappa*u_ref^2)
- *   t_hot_field    must be NULL in this build. */
+ *   t_hot_field    NULL (the hot wall is at t_hot), or a DEVICE array of
+ *                  nj*nk doubles, j fastest: the hot-wall temperature next
+ *                  to each (j, k) row.  Borrowed; it must stay valid until
+ *                  the work of every call given it has completed.  Its
+ *                  values enter the wall ghosts and the Nusselt integral;
+ *                  cavity_init still starts T linear between t_hot and
+ *                  t_cold.  The normalisation of the Nusselt number keeps
+ *                  the scalar t_hot - t_cold. */
 typedef struct {
     double Ra, Pr, cfl, eps4, kappa, u_ref, t_hot, t_cold, t_inf;
     const void* t_hot_field;
@@ -194,8 +201,45 @@ int cavity_residual_norm(const cav_grid* grid, const void* ws, size_t ws_bytes,
 int cavity_nusselt(const cav_grid* grid, const cav_params* prm, const void* q,
                    void* ws, size_t ws_bytes, double* out, hipStream_t stream);
 
-/* Discrete adjoint of one step (reverse mode) -- not available in this
- * build: always returns CAV_ENOSYS and enqueues nothing. */
+/* ---- discrete adjoint (reverse mode), FP64 only ------------------------
+ * Objective: the mean hot-wall Nusselt number J = Nu(q^N) of the state
+ * after N steps (cavity_nusselt).  Parameters: the hot-wall temperatures
+ * Theta (t_hot_field, or t_hot on every row) and Ra.  The adjoint of one
+ * step is the transpose of the exact derivative of the step that
+ * cavity_step computes (Sec. 2, Eq. 1-3: wall ghosts, residual, local time
+ * step, explicit update, centre rescale of p), written by hand; at the
+ * non-smooth points it takes one side: |u| has slope +1 at u = 0,
+ * beta^2 = max(|V|^2, kappa u_ref^2) follows |V|^2 only where strictly
+ * larger, dt follows the convective limit only where strictly smaller.
+ * The halo exchange of the virtual split is the identity on the state, so
+ * it has no adjoint term.
+ * A gradient is formed as: lam = cavity_nusselt_adjoint; for n = N-1 .. 0:
+ * cavity_adjoint_step(q^n, lam -> lam); then lam is dJ/dq^0 on the interior
+ * cells, dj_dthot dJ/dTheta and dj_dra dJ/dRa (both zeroed by the caller
+ * first).  q^n must be the states of the forward run (kept, or recomputed
+ * from checkpoints); every call must get the same params as the forward. */
+
+/* Bytes of the workspace cavity_adjoint_step needs (8 + blocks + 41 values
+ * per cell, in doubles); 0 for an invalid grid or a CAV_F32 grid. */
+size_t cavity_adjoint_workspace_bytes(const cav_grid* grid);
+
+/* Cotangent of J = Nu(q): writes lam (device, state layout, interior cells;
+ * zero except T in the first two cells off the hot wall) and ADDS dNu/dTheta
+ * (8 ni / (3 nj nk (t_hot - t_cold)) per row) into dj_dthot (device, nj*nk
+ * doubles, j fastest; NULL to skip).  Asynchronous on `stream`.
+ * CAV_EINVAL for a CAV_F32 grid or t_hot == t_cold. */
+int cavity_nusselt_adjoint(const cav_grid* grid, const cav_params* prm, void* lam,
+                           double* dj_dthot, hipStream_t stream);
+
+/* One reverse step: given lam_in = dJ/dq^{n+1} (device, state layout,
+ * interior cells read) and q_n (device, the state the forward step started
+ * from, interior cells read), writes lam_out = dJ/dq^n on the interior cells
+ * (its ghost cells are used as scratch and left unspecified) and ADDS this
+ * step's terms into dj_dthot (device, nj*nk doubles, j fastest) and dj_dra
+ * (device, 1 double); either may be NULL to skip it.  lam_out may equal
+ * lam_in; neither may alias q_n.  ws: device, >=
+ * cavity_adjoint_workspace_bytes.  Eight launches on `stream`, no
+ * allocation, no synchronisation.  CAV_EINVAL for a CAV_F32 grid. */
 int cavity_adjoint_step(const cav_grid* grid, const cav_params* prm,
                         const void* q_n, const void* lam_in, void* lam_out,
                         void* ws, size_t ws_bytes, double* dj_dthot,
@@ -210,7 +254,7 @@ int cavity_adjoint_step(const cav_grid* grid, const cav_params* prm,
  * k-chunk length.  There is no halo exchange in the batched form. */
 typedef struct {
     cav_grid grid;          /* member grid; dtype must match the batch      */
-    cav_params params;      /* member parameters (t_hot_field NULL)         */
+    cav_params params;      /* member parameters                             */
     void* q;                /* device state, cavity_state_elems(grid) elems */
     void* q_tmp;            /* device scratch state, same size, distinct    */
     void* ws;               /* device workspace                              */

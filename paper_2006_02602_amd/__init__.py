@@ -63,10 +63,18 @@ class Params:
     t_hot: float = 1.0
     t_cold: float = 0.0
     t_inf: float = 0.5
+    # None, or a float64 GPU tensor of nj*nk hot-wall temperatures (j fastest)
+    t_hot_field: object = field(default=None, compare=False)
 
     def c(self) -> CavParams:
+        f = self.t_hot_field
+        if f is not None:
+            import torch
+            if not (f.is_cuda and f.dtype == torch.float64 and f.is_contiguous()):
+                raise ValueError("t_hot_field must be a contiguous float64 GPU tensor")
+            f = f.data_ptr()
         return CavParams(self.Ra, self.Pr, self.cfl, self.eps4, self.kappa, self.u_ref,
-                         self.t_hot, self.t_cold, self.t_inf, None)
+                         self.t_hot, self.t_cold, self.t_inf, f)
 
 
 @dataclass(frozen=True)
@@ -190,6 +198,15 @@ def cavity_nusselt(grid, params, q, ws, stream=None) -> float:
     check(lib().cavity_nusselt(ctypes.byref(_grid(grid)), ctypes.byref(_params(params)), qp, wp, wb,
                                ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+def cavity_adjoint_workspace_bytes(grid) -> int:
+    return int(lib().cavity_adjoint_workspace_bytes(ctypes.byref(_grid(grid))))
+
+
+def cavity_nusselt_adjoint(grid, params, lam, dj_dthot, stream=None) -> None:
+    check(lib().cavity_nusselt_adjoint(ctypes.byref(_grid(grid)), ctypes.byref(_params(params)), _ptr(lam)[0],
+                                       _ptr(dj_dthot)[0], _stream(stream)))
 
 
 def cavity_adjoint_step(grid, params, q_n, lam_in, lam_out, ws, dj_dthot, dj_dra, stream=None) -> None:

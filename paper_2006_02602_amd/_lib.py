@@ -24,7 +24,8 @@ ERROR_NAMES = {CAV_EINVAL: "CAV_EINVAL", CAV_ESIZE: "CAV_ESIZE", CAV_EHIP: "CAV_
 
 # every function include/cavity.h declares
 EXPORTS = ("cavity_layout", "cavity_state_elems", "cavity_workspace_bytes", "halo_buffer_bytes", "cavity_init",
-           "cavity_step", "halo_pack", "halo_unpack", "cavity_residual_norm", "cavity_nusselt", "cavity_adjoint_step",
+           "cavity_step", "halo_pack", "halo_unpack", "cavity_residual_norm", "cavity_nusselt",
+           "cavity_adjoint_workspace_bytes", "cavity_nusselt_adjoint", "cavity_adjoint_step",
            "cavity_batch_table_bytes", "cavity_batch_build", "cavity_batch_step", "cavity_batch_graph_create",
            "cavity_batch_graph_launch", "cavity_batch_graph_destroy",
            "cavity_last_error", "cavity_timing_enable", "cavity_timing_read")
@@ -105,6 +106,10 @@ def lib():
     L.cavity_residual_norm.argtypes = [G, vp, sz, dp, vp]
     L.cavity_nusselt.restype = ctypes.c_int
     L.cavity_nusselt.argtypes = [G, Pp, vp, vp, sz, dp, vp]
+    L.cavity_adjoint_workspace_bytes.restype = sz
+    L.cavity_adjoint_workspace_bytes.argtypes = [G]
+    L.cavity_nusselt_adjoint.restype = ctypes.c_int
+    L.cavity_nusselt_adjoint.argtypes = [G, Pp, vp, vp, vp]
     L.cavity_adjoint_step.restype = ctypes.c_int
     L.cavity_adjoint_step.argtypes = [G, Pp, vp, vp, vp, vp, sz, vp, vp, vp]
     BM, BP = ctypes.POINTER(CavBatchMember), ctypes.POINTER(CavBatch)

@@ -135,7 +135,6 @@ int check_params(const cav_params* p)
     if (!(p->cfl > 0)) return fail(CAV_EINVAL, "cfl must be > 0");
     if (p->eps4 < 0 || p->kappa < 0 || p->u_ref < 0)
         return fail(CAV_EINVAL, "eps4, kappa and u_ref must be >= 0");
-    if (p->t_hot_field) return fail(CAV_EINVAL, "t_hot_field is not supported by this build (pass NULL)");
     return CAV_OK;
 }
 
@@ -156,6 +155,7 @@ Coef coef_of(const cav_grid* g, const cav_params* p)
     c.dt_visc = 1.0 / (2.0 * dmax * (nx * nx + ny * ny + nz * nz));
     c.t_hot = p->t_hot;
     c.t_cold = p->t_cold;
+    c.t_hot_field = static_cast<const double*>(p->t_hot_field);
     return c;
 }
 
@@ -393,7 +393,7 @@ int cavity_init(const cav_grid* grid, const cav_params* prm, uint64_t seed, doub
     if (!q) return fail(CAV_EINVAL, "q is NULL");
     if (!std::isfinite(noise_amp)) return fail(CAV_EINVAL, "noise_amp must be finite");
     const Dims d = dims_of(grid);
-    const Bcs bc{prm->t_hot, prm->t_cold};
+    const Bcs bc{prm->t_hot, prm->t_cold, static_cast<const double*>(prm->t_hot_field)};
     const bool f32 = grid->dtype == CAV_F32;
     hipError_t e = run("init", stream, [&] {
         return f32 ? launch_init<float>(d, prm->t_hot, prm->t_cold, seed, noise_amp, state_of<float>(q, d), stream)
@@ -483,10 +483,10 @@ int cavity_nusselt(const cav_grid* grid, const cav_params* prm, const void* q, v
     const size_t need = ws_bytes_of(d);
     if (ws_bytes < need) return fail(CAV_ESIZE, "ws_bytes %zu < required %zu", ws_bytes, need);
     double* slot = static_cast<double*>(ws) + 6;
+    const Bcs bc{prm->t_hot, prm->t_cold, static_cast<const double*>(prm->t_hot_field)};
     hipError_t e = run("nusselt", stream, [&] {
-        return grid->dtype == CAV_F32
-                   ? launch_nusselt<float>(d, prm->t_hot, prm->t_cold, cstate_of<float>(q, d), slot, stream)
-                   : launch_nusselt<double>(d, prm->t_hot, prm->t_cold, cstate_of<double>(q, d), slot, stream);
+        return grid->dtype == CAV_F32 ? launch_nusselt<float>(d, bc, cstate_of<float>(q, d), slot, stream)
+                                      : launch_nusselt<double>(d, bc, cstate_of<double>(q, d), slot, stream);
     });
     if (e != hipSuccess) return hip_fail("nusselt launch", e);
     e = hipMemcpyAsync(out, slot, sizeof(double), hipMemcpyDeviceToHost, stream);
@@ -496,10 +496,49 @@ int cavity_nusselt(const cav_grid* grid, const cav_params* prm, const void* q, v
     return CAV_OK;
 }
 
-int cavity_adjoint_step(const cav_grid*, const cav_params*, const void*, const void*, void*, void*, size_t,
-                        double*, double*, hipStream_t)
+size_t cavity_adjoint_workspace_bytes(const cav_grid* grid)
 {
-    return fail(CAV_ENOSYS, "cavity_adjoint_step is not available in this build");
+    if (check_grid(grid) != CAV_OK || grid->dtype != CAV_F64) return 0;
+    return adjoint_ws_doubles(dims_of(grid)) * sizeof(double);
+}
+
+int cavity_nusselt_adjoint(const cav_grid* grid, const cav_params* prm, void* lam, double* dj_dthot,
+                           hipStream_t stream)
+{
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_params(prm))) return rc;
+    if (grid->dtype != CAV_F64) return fail(CAV_EINVAL, "the adjoint is available for CAV_F64 only");
+    if (!lam) return fail(CAV_EINVAL, "lam is NULL");
+    if (prm->t_hot == prm->t_cold) return fail(CAV_EINVAL, "t_hot == t_cold: the Nusselt number is undefined");
+    const Dims d = dims_of(grid);
+    const double scale = ((double)grid->ni / 3.0) / ((double)grid->nj * (double)grid->nk) / (prm->t_hot - prm->t_cold);
+    hipError_t e = run("nusselt_seed", stream, [&] {
+        return launch_nusselt_seed(d, scale, state_of<double>(lam, d), dj_dthot, stream);
+    });
+    if (e != hipSuccess) return hip_fail("nusselt seed launch", e);
+    return CAV_OK;
+}
+
+int cavity_adjoint_step(const cav_grid* grid, const cav_params* prm, const void* q_n, const void* lam_in,
+                        void* lam_out, void* ws, size_t ws_bytes, double* dj_dthot, double* dj_dra,
+                        hipStream_t stream)
+{
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_params(prm))) return rc;
+    if (grid->dtype != CAV_F64) return fail(CAV_EINVAL, "the adjoint is available for CAV_F64 only");
+    if (!q_n || !lam_in || !lam_out || !ws) return fail(CAV_EINVAL, "q_n, lam_in, lam_out and ws must not be NULL");
+    if (lam_out == q_n || lam_in == q_n) return fail(CAV_EINVAL, "the cotangents must not alias q_n");
+    const Dims d = dims_of(grid);
+    const size_t need = adjoint_ws_doubles(d) * sizeof(double);
+    if (ws_bytes < need) return fail(CAV_ESIZE, "ws_bytes %zu < required %zu", ws_bytes, need);
+    const Coef c = coef_of(grid, prm);
+    hipError_t e = run("adjoint_step", stream, [&] {
+        return launch_adjoint_step(d, c, prm->Ra, cstate_of<double>(q_n, d), cstate_of<double>(lam_in, d),
+                                   state_of<double>(lam_out, d), static_cast<double*>(ws), dj_dthot, dj_dra,
+                                   stream);
+    });
+    if (e != hipSuccess) return hip_fail("adjoint launch", e);
+    return CAV_OK;
 }
 
 size_t cavity_batch_table_bytes(int32_t n, const cav_batch_member* members)

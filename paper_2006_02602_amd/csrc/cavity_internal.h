@@ -53,6 +53,7 @@ struct Coef {
     double cfl;
     double dt_visc;           // 1 / (2 max(nu, alpha) (nx^2 + ny^2 + nz^2))
     double t_hot, t_cold;     // hot (x = 0) and cold (x = 1) wall temperatures
+    const double* t_hot_field;   // NULL, or nj*nk hot-wall temperatures (device, j fastest)
 };
 
 // Sweep launch geometry.
@@ -69,6 +70,7 @@ SweepGeom sweep_geom(const Dims& d, int slots);     // slots: blocks resident at
 
 struct Bcs {
     double t_hot, t_cold;
+    const double* t_hot_field;   // NULL, or nj*nk hot-wall temperatures (device, j fastest)
 };
 
 // Halo geometry (virtual split, widths) shared by pack and unpack.
@@ -116,7 +118,14 @@ hipError_t launch_batch(const BatchCav* cavs, const BatchItem* items, int nitems
                         int nblocks, hipStream_t s);
 hipError_t launch_batch_norms(const BatchCav* cavs, int members, hipStream_t s);
 template <typename Real>
-hipError_t launch_nusselt(const Dims& d, double t_hot, double t_cold, CStateT<Real> q, double* out,
+hipError_t launch_nusselt(const Dims& d, const Bcs& b, CStateT<Real> q, double* out,
                           hipStream_t s);
+
+// Discrete adjoint (FP64): workspace size in doubles, one reverse step, and
+// the cotangent of the mean hot-wall Nusselt number (scale = ni/3/(nj nk dT)).
+size_t adjoint_ws_doubles(const Dims& d);
+hipError_t launch_adjoint_step(const Dims& d, const Coef& c, double Ra, CStateT<double> q, CStateT<double> lam_in,
+                               StateT<double> lam_out, double* ws, double* dthot, double* dra, hipStream_t s);
+hipError_t launch_nusselt_seed(const Dims& d, double scale, StateT<double> lam, double* dthot, hipStream_t s);
 
 }  // namespace cav

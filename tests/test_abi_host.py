@@ -103,10 +103,11 @@ def test_step_zero_steps_is_a_no_op():
     assert _step_rc(nsteps=0) == C.CAV_OK
 
 
-def test_t_hot_field_rejected():
-    p = C.Params().c()
-    p.t_hot_field = 0x1000
-    assert _step_rc(params=p) == C.CAV_EINVAL
+def test_t_hot_field_must_be_a_float64_gpu_tensor():
+    import torch
+    with pytest.raises(ValueError):
+        C.Params(t_hot_field=torch.ones(4, dtype=torch.float64)).c()
+    assert C.Params().c().t_hot_field is None
 
 
 def test_pack_unpack_and_norm_validation():
@@ -124,10 +125,36 @@ def test_pack_unpack_and_norm_validation():
     assert L.cavity_init(None, None, 0, 0.0, FAKE, None) == C.CAV_EINVAL
 
 
-def test_adjoint_not_available():
-    with pytest.raises(C.CavError) as e:
-        C.cavity_adjoint_step(C.Grid(16, 16, 16), C.Params(), None, None, None, None, None, None, stream=0)
-    assert e.value.code == C.CAV_ENOSYS
+def test_adjoint_validation():
+    """The adjoint is FP64 only; sizes, NULLs and aliasing are rejected
+    before anything is launched."""
+    L = C.lib()
+    g64, g32 = C.Grid(16, 12, 10), C.Grid(16, 12, 10, dtype=C.CAV_F32)
+    need = C.cavity_adjoint_workspace_bytes(g64)
+    # 8 head doubles + per-block partials (rounded to 8) + 41 values per cell
+    nb = max(-(-16 * 12 * 10 // 256), -(-12 * 10 // 256))
+    assert need == 8 * (8 + -(-nb // 8) * 8 + 41 * 16 * 12 * 10)
+    assert C.cavity_adjoint_workspace_bytes(g32) == 0
+    G, P = ctypes.byref(g64.c()), ctypes.byref(C.Params().c())
+    a, b = FAKE, ctypes.c_void_p(FAKE.value + 4096)
+    assert L.cavity_adjoint_step(ctypes.byref(g32.c()), P, a, b, b, b, need, None, None, None) == C.CAV_EINVAL
+    assert L.cavity_adjoint_step(G, P, a, b, b, b, need - 8, None, None, None) == C.CAV_ESIZE
+    assert L.cavity_adjoint_step(G, P, a, a, b, b, need, None, None, None) == C.CAV_EINVAL
+    assert L.cavity_adjoint_step(G, P, None, b, b, b, need, None, None, None) == C.CAV_EINVAL
+    assert L.cavity_nusselt_adjoint(ctypes.byref(g32.c()), P, a, None, None) == C.CAV_EINVAL
+    same = C.Params(t_hot=0.5, t_cold=0.5).c()
+    assert L.cavity_nusselt_adjoint(G, ctypes.byref(same), a, None, None) == C.CAV_EINVAL
+    assert L.cavity_nusselt_adjoint(G, P, None, None, None) == C.CAV_EINVAL
+
+
+def test_checkpoint_segments():
+    from paper_2006_02602_amd.adjoint import segments
+    assert segments(400, 20) == [(s, 20) for s in range(0, 400, 20)]
+    assert segments(24, 7) == [(0, 7), (7, 7), (14, 7), (21, 3)]
+    assert segments(0, 5) == []
+    assert segments(3, 10) == [(0, 3)]
+    with pytest.raises(ValueError):
+        segments(10, 0)
 
 
 def test_timing_read_empty():

@@ -1,0 +1,220 @@
+"""GPU tests of the discrete adjoint (cavity_nusselt_adjoint,
+cavity_adjoint_step) and of the hot-wall temperature field it
+differentiates with respect to.
+
+  * forward with a hot-wall field against the C oracle (1e-12);
+  * gradient . direction against the complex-step tangent oracle
+    (oracle/tangent.py) at 16^3 and on a ragged grid, in both time-step
+    regimes, along state, wall and Ra directions (1e-9);
+  * gradient against central finite differences of the library's own
+    forward at 64^3, Ra 1e4, 400 steps, checkpoints every 20, along 16
+    seeded directions (1e-6);
+  * checkpoint interval and in-place cotangents change nothing (bit-exact);
+  * the torch.autograd wrapper returns the same gradient.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import tangent as TG
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def C():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2006_02602_amd as C
+    C.lib()
+    return C
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def theta_of(n, seed, amp=0.05):
+    ni, nj, nk = n
+    return 1.0 + amp * np.random.default_rng(seed).uniform(-1, 1, nj * nk)
+
+
+def gpu_state(C, g, q):
+    import torch
+    t = torch.zeros(C.cavity_state_elems(g), dtype=torch.float64, device="cuda")
+    C.state_view(g, t).copy_(torch.from_numpy(np.ascontiguousarray(q)))
+    return t
+
+
+def interior_np(C, g, t):
+    import torch
+    torch.cuda.synchronize()
+    G = g.ng
+    return C.state_view(g, t)[:, G:G + g.nk, G:G + g.nj, G:G + g.ni].cpu().numpy()
+
+
+def gradient(C, n, Ra, theta, q0, nsteps, every):
+    import torch
+    from paper_2006_02602_amd.adjoint import NusseltAdjoint
+    g = C.Grid(*n)
+    adj = NusseltAdjoint(g, C.Params(), nsteps, every)
+    th = torch.from_numpy(theta).cuda()
+    J = adj.forward(th, Ra, gpu_state(C, g, q0))
+    dth, dra, dq0 = adj.backward()
+    torch.cuda.synchronize()
+    return J, dth.cpu().numpy(), float(dra.cpu()[0]), interior_np(C, g, dq0)
+
+
+@pytest.mark.parametrize("n,Ra", [((16, 16, 16), 1e5), ((19, 13, 11), 1e3)])
+def test_forward_with_wall_field_matches_oracle(C, n, Ra):
+    import torch
+    say("wall field forward", n, Ra)
+    theta = theta_of(n, 4)
+    P = O.Problem(*n, Ra=Ra, t_hot_field=theta)
+    q0 = O.init(P, 8, 1e-3)
+    ref = q0.copy()
+    O.step(P, ref, 30)
+    g = C.Grid(*n)
+    th = torch.from_numpy(theta).cuda()
+    prm = C.Params(Ra=Ra, t_hot_field=th)
+    cav = C.Cavity(g, prm)
+    cav.q.copy_(gpu_state(C, g, q0))
+    cav.step(30)
+    got = interior_np(C, g, cav.q)
+    want = P.interior(ref)
+    for f in range(5):
+        assert np.abs(got[f] - want[f]).max() <= 1e-12 * np.abs(want[f]).max(), f
+    nu, nu_ref = cav.nusselt(), O.nusselt_hot(P, ref)
+    assert abs(nu - nu_ref) <= 1e-12 * abs(nu_ref)
+    # a uniform field equal to t_hot gives the scalar problem bit for bit
+    a = C.Cavity(g, C.Params(Ra=Ra, t_hot_field=torch.ones(n[1] * n[2], dtype=torch.float64, device="cuda")))
+    b = C.Cavity(g, C.Params(Ra=Ra))
+    a.q.copy_(gpu_state(C, g, q0))
+    b.q.copy_(a.q)
+    a.step(7)
+    b.step(7)
+    assert np.array_equal(interior_np(C, g, a.q), interior_np(C, g, b.q))
+
+
+CASES = [((16, 16, 16), 1e3, 20), ((16, 16, 16), 1e6, 20), ((19, 13, 11), 1e5, 15)]
+
+
+@pytest.mark.parametrize("n,Ra,steps", CASES)
+def test_gradient_matches_tangent_oracle(C, n, Ra, steps):
+    say("adjoint vs tangent", n, Ra, steps)
+    ni, nj, nk = n
+    theta = theta_of(n, 5)
+    P = O.Problem(*n)
+    q0 = O.init(P, 6, 1e-3)
+    J, dth, dra, dq0 = gradient(C, n, Ra, theta, q0, steps, every=7)
+    rng = np.random.default_rng(7)
+    for trial in range(2):
+        dq = np.zeros_like(q0)
+        P.interior(dq)[:] = rng.uniform(-1, 1, (5, nk, nj, ni))
+        dt = rng.uniform(-1, 1, nj * nk)
+        for name, kw, got in (("q", dict(dq=dq), float(np.sum(dq0 * P.interior(dq)))),
+                              ("theta", dict(dtheta=dt), float(dth @ dt)),
+                              ("Ra", dict(dRa=Ra), dra * Ra)):
+            Jt, want = TG.nusselt_tangent(*n, Ra, theta, q0, steps, **kw)
+            say("  %-5s adjoint % .15e tangent % .15e" % (name, got, want))
+            assert abs(J - Jt) <= 1e-12 * abs(Jt)
+            assert abs(got - want) <= 1e-9 * max(abs(want), 1e-6 * abs(Jt)), (name, got, want)
+
+
+def test_gradient_matches_finite_differences_64(C):
+    """64^3, Ra 1e4, 400 steps, checkpoints every 20; theta = 1 + 0.05 noise
+    (seed 5).  16 seeded directions in (theta, Ra): 12 random unit wall
+    directions, 2 uniform wall shifts, 2 in Ra; central differences of the
+    library's forward with h = 1e-6 (relative for Ra)."""
+    import torch
+    say("adjoint vs FD 64^3")
+    n, Ra, steps = (64, 64, 64), 1e4, 400
+    theta = theta_of(n, 5)
+    g = C.Grid(*n)
+    P = O.Problem(*n)
+    q0 = O.init(P, 9, 1e-3)
+    J, dth, dra, _ = gradient(C, n, Ra, theta, q0, steps, every=20)
+    q0d = gpu_state(C, g, q0)
+
+    def nu(th, ra):
+        cav = C.Cavity(g, C.Params(Ra=ra, t_hot_field=torch.from_numpy(th).cuda()))
+        cav.q.copy_(q0d)
+        cav.step(steps)
+        return cav.nusselt()
+
+    rng = np.random.default_rng(10)
+    dirs = []
+    for _ in range(12):
+        v = rng.standard_normal(n[1] * n[2])
+        dirs.append((v / np.linalg.norm(v), 0.0))
+    ones = np.ones(n[1] * n[2]) / n[1]
+    dirs += [(ones, 0.0), (-ones, 0.0), (np.zeros_like(ones), Ra), (np.zeros_like(ones), -Ra)]
+    h = 1e-6
+    worst = 0.0
+    for v, r in dirs:
+        fd = (nu(theta + h * v, Ra + h * r) - nu(theta - h * v, Ra - h * r)) / (2 * h)
+        got = float(dth @ v) + dra * r
+        err = abs(got - fd) / max(abs(fd), 1e-12)
+        worst = max(worst, err)
+        say("  adjoint % .12e  fd % .12e  rel %.2e" % (got, fd, err))
+        # truncation O(h^2); rounding ~ 1e-14 |J| / h
+        assert abs(got - fd) <= 1e-6 * abs(fd) + 1e-14 * abs(J) / h
+    say("  worst rel", worst)
+
+
+def test_checkpoint_interval_and_in_place_change_nothing(C):
+    say("adjoint checkpoint invariance")
+    n, Ra, steps = (16, 12, 10), 1e5, 24
+    theta = theta_of(n, 2)
+    q0 = O.init(O.Problem(*n), 3, 1e-3)
+    ref = gradient(C, n, Ra, theta, q0, steps, every=steps)
+    for every in (1, 5, 20):
+        got = gradient(C, n, Ra, theta, q0, steps, every=every)
+        assert got[0] == ref[0]
+        assert np.array_equal(got[1], ref[1]) and got[2] == ref[2] and np.array_equal(got[3], ref[3]), every
+
+
+def test_adjoint_step_out_of_place_equals_in_place(C):
+    import torch
+    say("adjoint in place")
+    n = (16, 16, 16)
+    g = C.Grid(*n)
+    prm = C.Params(Ra=1e5)
+    q = gpu_state(C, g, O.init(O.Problem(*n), 4, 1e-3))
+    lam0 = gpu_state(C, g, np.random.default_rng(1).standard_normal(O.Problem(*n).shape))
+    ws = torch.empty(C.cavity_adjoint_workspace_bytes(g) // 8, dtype=torch.float64, device="cuda")
+    outs = []
+    for inplace in (False, True):
+        lam = lam0.clone()
+        out = lam if inplace else torch.full_like(lam, float("nan"))
+        dth = torch.zeros(n[1] * n[2], dtype=torch.float64, device="cuda")
+        dra = torch.zeros(1, dtype=torch.float64, device="cuda")
+        C.cavity_adjoint_step(g, prm, q, lam, out, ws, dth, dra)
+        outs.append((interior_np(C, g, out), dth.cpu().numpy(), float(dra.cpu()[0])))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1]) and outs[0][2] == outs[1][2]
+    assert np.isfinite(outs[0][0]).all()
+
+
+def test_autograd_function(C):
+    import torch
+    from paper_2006_02602_amd import adjoint
+    say("adjoint autograd")
+    n, Ra, steps = (16, 16, 16), 1e5, 12
+    theta = theta_of(n, 3)
+    q0 = O.init(O.Problem(*n), 5, 1e-3)
+    g = C.Grid(*n)
+    th = torch.from_numpy(theta).cuda().requires_grad_(True)
+    ra = torch.tensor(Ra, dtype=torch.float64, requires_grad=True)
+    q0d = gpu_state(C, g, q0).requires_grad_(True)
+    J = adjoint.nusselt(th, ra, q0d, g, C.Params(), steps, every=5)
+    J.backward()
+    ref = gradient(C, n, Ra, theta, q0, steps, every=5)
+    assert float(J) == ref[0]
+    assert np.array_equal(th.grad.cpu().numpy(), ref[1])
+    assert float(ra.grad) == ref[2]
+    assert np.array_equal(interior_np(C, g, q0d.grad), ref[3])
