@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
 SWEEP_BYTES_PER_CELL = 80      # read 5 + write 5 FP64 fields per interior cell
+ADJ_MIN_BYTES_PER_CELL = 120   # reverse step: read q^n and lambda, write lambda (5 FP64 fields each)
 PAPER_SSSPNT_P100 = 93.8       # single-GPU row of Tables 3-4 (P100, 256^3, no halo)
 
 
@@ -166,6 +167,93 @@ def batch_leg(C, torch, steps):
             "GBs_algorithmic": 40 * b.cells / (dt / steps) / 1e9, "norms_finite": norms_ok}
 
 
+def overlap_leg(C, torch, grid, prm, splits, widths, steps):
+    """Whole steps with the halo exchange: unsplit (cavity_step) against the
+    interior/exterior split (cavity_step_overlap) with the exchange on the
+    same stream and on a second stream; per split, ms per step."""
+    out = []
+    comm = torch.cuda.Stream()
+    for split in splits:
+        h = C.Halo(split, widths)
+        cav = C.Cavity(grid, prm, h).init(2)
+        row = {"split": "x".join(map(str, split)), "widths": list(widths)}
+        for name, fn in (("unsplit", lambda: cav.step(steps)),
+                         ("split_one_stream", lambda: cav.step_overlap(steps)),
+                         ("split_two_streams", lambda: cav.step_overlap(steps, comm_stream=comm))):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            row[name + "_ms_per_step"] = 1e3 * (time.perf_counter() - t0) / steps
+        C.cavity_timing_read()
+        C.cavity_timing_enable(True)
+        cav.step_overlap(steps, comm_stream=comm)
+        torch.cuda.synchronize()
+        C.cavity_timing_enable(False)
+        kt = C.cavity_timing_read()
+        row["split_kernels_us"] = {k: round(1e3 * ms / n, 2) for k, (n, ms) in sorted(kt.items())
+                                   if k in ("interior", "interior_norm", "exterior", "exterior_norm", "halo_pack", "halo_unpack")}
+        out.append(row)
+        del cav
+    return out
+
+
+def adjoint_leg(C, torch):
+    """Gradient of the hot-wall Nusselt number (64^3, Ra 1e4, 400 steps,
+    checkpoints every 20): forward with checkpoints, then the reverse sweep
+    with segment recomputation; plus the reverse step alone at 256^3."""
+    from paper_2006_02602_amd.adjoint import NusseltAdjoint
+    from paper_2006_02602_amd.configs import ADJOINT as A
+    g = A.grid
+    th = torch.from_numpy(A.theta()).cuda()
+    q0 = torch.zeros(C.cavity_state_elems(g), dtype=torch.float64, device="cuda")
+    C.cavity_init(g, C.Params(Ra=A.Ra), A.seed, 1e-3, q0)
+    adj = NusseltAdjoint(g, C.Params(), A.steps, A.every)
+    adj.forward(th, A.Ra, q0)            # warm-up
+    adj.backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = adj.forward(th, A.Ra, q0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    C.cavity_timing_read()
+    C.cavity_timing_enable(True)
+    dth, dra, _ = adj.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    C.cavity_timing_enable(False)
+    kt = C.cavity_timing_read()
+    fwd, bwd = t1 - t0, t2 - t1
+    n_rev, rev_ms = kt.get("adjoint_step", (0, 0.0))
+    out = {"workload": A.name, "n": A.n, "Ra": A.Ra, "steps": A.steps, "checkpoint_every": A.every,
+           "nusselt": J, "dJ_dRa": float(dra.cpu()[0]), "dJ_dtheta_sum": float(dth.sum()),
+           "forward_ms": 1e3 * fwd, "gradient_ms": 1e3 * bwd, "gradient_over_forward": bwd / fwd,
+           "reverse_step_us": 1e3 * rev_ms / max(n_rev, 1)}
+    # the reverse step alone at 256^3 (one GPU's share of the headline grid)
+    g2 = C.Grid.cube(256)
+    q = torch.zeros(C.cavity_state_elems(g2), dtype=torch.float64, device="cuda")
+    C.cavity_init(g2, C.Params(Ra=1e5), 2, 1e-3, q)
+    lam = torch.zeros_like(q)
+    C.cavity_nusselt_adjoint(g2, C.Params(Ra=1e5), lam, None)
+    aws = torch.empty(C.cavity_adjoint_workspace_bytes(g2) // 8, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        C.cavity_adjoint_step(g2, C.Params(Ra=1e5), q, lam, lam, aws, None, None)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        C.cavity_adjoint_step(g2, C.Params(Ra=1e5), q, lam, lam, aws, None, None)
+    torch.cuda.synchronize()
+    us = 1e6 * (time.perf_counter() - t0) / reps
+    cells = g2.ncell
+    out["reverse_step_256cubed_us"] = us
+    out["reverse_step_256cubed_GBs_min_traffic"] = ADJ_MIN_BYTES_PER_CELL * cells / (us * 1e-6) / 1e9
+    out["reverse_step_min_bytes_per_cell"] = ADJ_MIN_BYTES_PER_CELL
+    del aws, lam, q
+    return out
+
+
 def cpu_baseline(wl, budget_s):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     workload (same grid, parameters and halo; fewer steps)."""
@@ -196,6 +284,8 @@ def main():
     ap.add_argument("--no-halo-bench", action="store_true")
     ap.add_argument("--no-f32", action="store_true", help="skip the FP32 precision-form leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the discrete-adjoint leg")
+    ap.add_argument("--no-overlap", action="store_true", help="skip the interior/exterior split leg")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
@@ -280,6 +370,19 @@ def main():
         batch = batch_leg(C, torch, 100)
         log("bench: batch", batch)
 
+    ovl = None
+    if not args.no_overlap:
+        log("bench: interior/exterior split ...")
+        ovl = overlap_leg(C, torch, grid, prm, wl.splits, wl.widths, 20)
+        for r in ovl:
+            log("bench: overlap", r)
+
+    adj = None
+    if not args.no_adjoint:
+        log("bench: discrete adjoint (64^3, 400 steps) ...")
+        adj = adjoint_leg(C, torch)
+        log("bench: adjoint", adj)
+
     value = ncell * K / t_run
     line = {
         "metric": "grid-point updates/s + % HBM peak (stencil, pack/unpack); FP32 & batched vs FP64",
@@ -322,6 +425,11 @@ def main():
         if f32 is not None:
             batch["batch_over_f32_single_rate"] = batch["value"] / f32["value"]
         line["batch"] = batch
+    if ovl is not None:
+        line["overlap"] = ovl
+    if adj is not None:
+        adj["reverse_over_forward_step_256cubed"] = adj["reverse_step_256cubed_us"] / (1e3 * sw_ms)
+        line["adjoint"] = adj
     if not args.no_cpu:
         log("bench: CPU baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)

@@ -166,6 +166,26 @@ int cavity_step(const cav_grid* grid, const cav_params* prm, const cav_halo* hal
                 void* halo_buf, size_t halo_bytes, int32_t nsteps,
                 hipStream_t stream);
 
+/* cavity_step with the interior/exterior split of Sec. 4.7: per step the
+ * exchange (halo_pack, halo_unpack) runs on comm_stream while the cells
+ * whose stars reach no unpacked cell (the interior) are updated on
+ * `stream`; the cells within m of a cut (the exterior; m = the largest
+ * width[f] + reach of field f's star, reach 2 for p and 1 for u v w T) are
+ * updated on `stream` after the exchange.  Each cell goes through the same
+ * per-cell arithmetic as in cavity_step, so q after the call is bit-identical
+ * to cavity_step's; the residual norms agree to rounding (their partial sums
+ * are grouped by launch).  Every subdomain extent along a split axis must
+ * be >= 2m (CAV_EINVAL otherwise).  halo must not be NULL.  comm_stream
+ * may equal `stream` (no overlap, same results).  Ordering between the two
+ * streams uses two events created and destroyed by the call; when `stream`
+ * has completed, so has all work of the call.  Other arguments as for
+ * cavity_step; CAV_ESIZE when the norm partials of the split do not fit
+ * ws (only for grids with very few planes). */
+int cavity_step_overlap(const cav_grid* grid, const cav_params* prm, const cav_halo* halo,
+                        void* q, void* q_tmp, void* ws, size_t ws_bytes,
+                        void* halo_buf, size_t halo_bytes, int32_t nsteps,
+                        hipStream_t stream, hipStream_t comm_stream);
+
 /* Gather every halo segment of `halo` (layout: halo_buffer_bytes) from q
  * into the contiguous buffer buf (Sec. 4.5, Listings 1-2: the parallel
  * in-device pack of the "Optimized" versions; V3 covers i, j and k faces).

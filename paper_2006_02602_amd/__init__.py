@@ -168,6 +168,22 @@ def cavity_step(grid, params, halo, q, q_tmp, ws, halo_buf, nsteps: int, stream=
                             int(nsteps), _stream(stream)))
 
 
+def cavity_step_overlap(grid, params, halo, q, q_tmp, ws, halo_buf, nsteps: int, stream=None,
+                        comm_stream=None) -> None:
+    """cavity_step with the interior sweep overlapping the exchange on
+    comm_stream (default: the same stream)."""
+    qp, _ = _ptr(q)
+    tp, _ = _ptr(q_tmp)
+    wp, wb = _ptr(ws)
+    bp, bb = _ptr(halo_buf)
+    h = _halo(halo)
+    s = _stream(stream)
+    cs = s if comm_stream is None else _stream(comm_stream)
+    check(lib().cavity_step_overlap(ctypes.byref(_grid(grid)), ctypes.byref(_params(params)),
+                                    ctypes.byref(h) if h is not None else None, qp, tp, wp, wb, bp, bb,
+                                    int(nsteps), s, cs))
+
+
 def halo_pack(grid, halo, q, buf, stream=None) -> None:
     qp, _ = _ptr(q)
     bp, bb = _ptr(buf)
@@ -297,6 +313,13 @@ class Cavity:
 
     def step(self, nsteps: int) -> "Cavity":
         cavity_step(self.grid, self.params, self.halo, self.q, self.q_tmp, self.ws, self.buf, nsteps)
+        return self
+
+    def step_overlap(self, nsteps: int, comm_stream=None) -> "Cavity":
+        """Steps with the interior/exterior split; the exchange runs on
+        comm_stream (a torch.cuda.Stream) when given."""
+        cavity_step_overlap(self.grid, self.params, self.halo, self.q, self.q_tmp, self.ws, self.buf, nsteps,
+                            comm_stream=comm_stream)
         return self
 
     def norms(self):

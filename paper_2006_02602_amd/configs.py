@@ -71,3 +71,31 @@ def batch_workload(count: int = 96, seed: int = 4):
         r = (splitmix64(seed, 2 * c + 1) >> 11) * 2.0 ** -53
         out.append((edge, 10.0 ** (3.0 + 3.0 * r), seed * 1000 + c))
     return out
+
+
+# ---- discrete adjoint: gradient of the hot-wall Nusselt number ------------
+@dataclass(frozen=True)
+class AdjointWorkload:
+    """64^3 FP64 at Ra 1e4, 400 steps, checkpoints every 20; hot-wall
+    temperatures 1 + 0.05 (2r - 1) with r from SplitMix64(seed) output
+    j + nj k (53-bit uniform); initial state seeded like the parity case."""
+    name: str = "adjoint64_f64_ra1e4"
+    n: int = 64
+    Ra: float = 1e4
+    steps: int = 400
+    every: int = 20
+    seed: int = 5
+    amp: float = 0.05
+
+    @property
+    def grid(self) -> Grid:
+        return Grid.cube(self.n)
+
+    def theta(self):
+        import numpy as np
+        nj = nk = self.n
+        r = np.array([(splitmix64(self.seed, m) >> 11) * 2.0 ** -53 for m in range(nj * nk)])
+        return 1.0 + self.amp * (2.0 * r - 1.0)
+
+
+ADJOINT = AdjointWorkload()

@@ -348,6 +348,96 @@ int step_impl(const cav_grid* grid, const cav_params* prm, const cav_halo* halo,
     return CAV_OK;
 }
 
+// Interior/exterior split: margin m = the widest reach of an unpacked
+// layer into the stars (width + 2 for p, width + 1 for u v w T); exterior x
+// and y slabs in k chunks of 16 planes, longer if the norm partials would
+// not fit the workspace.
+int split_geom(const cav_grid* grid, const HaloGeom& hg, const SweepGeom& g, size_t ws_bytes, SplitGeom* out)
+{
+    const Dims d = dims_of(grid);
+    SplitGeom sg;
+    sg.m = 0;
+    for (int f = 0; f < NF; ++f)
+        if (hg.w[f] > 0) sg.m = std::max(sg.m, hg.w[f] + (f == FP ? 2 : 1));
+    const int n[3] = {grid->ni, grid->nj, grid->nk};
+    for (int a = 0; a < 3; ++a) {
+        sg.P[a] = sg.m > 0 ? hg.P[a] : 1;
+        sg.e[a] = n[a] / hg.P[a];
+        if (sg.P[a] > 1 && sg.e[a] < 2 * sg.m)
+            return fail(CAV_EINVAL, "subdomain extent %d along axis %d is below 2 x the exterior margin %d", sg.e[a], a,
+                        sg.m);
+    }
+    const size_t cap = (ws_bytes - WS_HEAD) / (NF * sizeof(double));
+    for (sg.kce = std::min(16, d.nk);; sg.kce = std::min(2 * sg.kce, d.nk)) {
+        if ((size_t)g.nblocks + exterior_blocks(d, g, sg) <= cap) break;
+        if (sg.kce == d.nk)
+            return fail(CAV_ESIZE, "workspace too small for the norm partials of the split sweep");
+    }
+    *out = sg;
+    return CAV_OK;
+}
+
+template <typename Real>
+int overlap_impl(const cav_grid* grid, const cav_params* prm, const HaloGeom& hg, void* q, void* q_tmp, void* ws,
+                 size_t ws_bytes, void* halo_buf, int32_t nsteps, hipStream_t stream, hipStream_t comm)
+{
+    int rc;
+    const Dims d = dims_of(grid);
+    const Coef c = coef_of(grid, prm);
+    const SweepGeom g = sweep_geom(d, device_slots());
+    SplitGeom sg;
+    if ((rc = split_geom(grid, hg, g, ws_bytes, &sg))) return rc;
+    const int nb_ext = exterior_blocks(d, g, sg);
+    double* wsd = static_cast<double*>(ws);
+    double* partials = reinterpret_cast<double*>(static_cast<char*>(ws) + WS_HEAD);
+    hipEvent_t ready = nullptr, exchanged = nullptr;
+    hipError_t e;
+    if ((e = hipEventCreateWithFlags(&ready, hipEventDisableTiming)) != hipSuccess) return hip_fail("event create", e);
+    if ((e = hipEventCreateWithFlags(&exchanged, hipEventDisableTiming)) != hipSuccess) {
+        hipEventDestroy(ready);
+        return hip_fail("event create", e);
+    }
+    auto done = [&](int r) {
+        hipEventDestroy(ready);
+        hipEventDestroy(exchanged);
+        return r;
+    };
+    void* cur = q;
+    void* nxt = q_tmp;
+    for (int n = 0; n < nsteps; ++n) {
+        const bool last = n == nsteps - 1;
+        // the exchange on `comm` once the state is complete
+        if ((e = hipEventRecord(ready, stream)) != hipSuccess) return done(hip_fail("event record", e));
+        if ((e = hipStreamWaitEvent(comm, ready, 0)) != hipSuccess) return done(hip_fail("stream wait", e));
+        if ((rc = do_halo(grid, hg, cur, halo_buf, true, comm))) return done(rc);
+        if ((rc = do_halo(grid, hg, cur, halo_buf, false, comm))) return done(rc);
+        if ((e = hipEventRecord(exchanged, comm)) != hipSuccess) return done(hip_fail("event record", e));
+        // interior meanwhile on `stream`, exterior after the exchange
+        e = run(last ? "interior_norm" : "interior", stream, [&] {
+            return launch_split<Real>(d, c, g, sg, false, cstate_of<Real>(cur, d), state_of<Real>(nxt, d), partials,
+                                      last, stream);
+        });
+        if (e != hipSuccess) return done(hip_fail("interior launch", e));
+        if ((e = hipStreamWaitEvent(stream, exchanged, 0)) != hipSuccess) return done(hip_fail("stream wait", e));
+        e = run(last ? "exterior_norm" : "exterior", stream, [&] {
+            return launch_split<Real>(d, c, g, sg, true, cstate_of<Real>(cur, d), state_of<Real>(nxt, d), partials,
+                                      last, stream);
+        });
+        if (e != hipSuccess) return done(hip_fail("exterior launch", e));
+        std::swap(cur, nxt);
+    }
+    const double ncell = (double)d.ni * d.nj * d.nk;
+    e = run("norm_finalize", stream,
+            [&] { return launch_norm_finalize(partials, g.nblocks + nb_ext, ncell, wsd, stream); });
+    if (e != hipSuccess) return done(hip_fail("norm finalize launch", e));
+    if (cur != q) {
+        const size_t bytes = (size_t)NF * field_elems(d) * sizeof(Real);
+        e = run("copy", stream, [&] { return hipMemcpyAsync(q, cur, bytes, hipMemcpyDeviceToDevice, stream); });
+        if (e != hipSuccess) return done(hip_fail("state copy", e));
+    }
+    return done(CAV_OK);
+}
+
 }  // namespace
 
 extern "C" {
@@ -430,6 +520,30 @@ int cavity_step(const cav_grid* grid, const cav_params* prm, const cav_halo* hal
     if (nsteps == 0) return CAV_OK;
     return grid->dtype == CAV_F32 ? step_impl<float>(grid, prm, halo, hg, q, q_tmp, ws, halo_buf, nsteps, stream)
                                   : step_impl<double>(grid, prm, halo, hg, q, q_tmp, ws, halo_buf, nsteps, stream);
+}
+
+int cavity_step_overlap(const cav_grid* grid, const cav_params* prm, const cav_halo* halo, void* q, void* q_tmp,
+                        void* ws, size_t ws_bytes, void* halo_buf, size_t halo_bytes, int32_t nsteps,
+                        hipStream_t stream, hipStream_t comm_stream)
+{
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_params(prm))) return rc;
+    if (nsteps < 0) return fail(CAV_EINVAL, "nsteps = %d must be >= 0", nsteps);
+    if (!halo) return fail(CAV_EINVAL, "halo is NULL (the split needs the exchange it overlaps)");
+    if (!q || !q_tmp || !ws) return fail(CAV_EINVAL, "q, q_tmp and ws must not be NULL");
+    if (q == q_tmp) return fail(CAV_EINVAL, "q and q_tmp must be distinct buffers");
+    const Dims d = dims_of(grid);
+    const size_t need_ws = ws_bytes_of(d);
+    if (ws_bytes < need_ws) return fail(CAV_ESIZE, "ws_bytes %zu < required %zu", ws_bytes, need_ws);
+    HaloGeom hg;
+    if ((rc = check_halo(grid, halo, &hg))) return rc;
+    const size_t need = halo_elems(hg) * (size_t)elem_size(grid->dtype);
+    if (need && !halo_buf) return fail(CAV_EINVAL, "halo_buf is NULL");
+    if (halo_bytes < need) return fail(CAV_ESIZE, "halo_bytes %zu < required %zu", halo_bytes, need);
+    if (nsteps == 0) return CAV_OK;
+    return grid->dtype == CAV_F32
+               ? overlap_impl<float>(grid, prm, hg, q, q_tmp, ws, ws_bytes, halo_buf, nsteps, stream, comm_stream)
+               : overlap_impl<double>(grid, prm, hg, q, q_tmp, ws, ws_bytes, halo_buf, nsteps, stream, comm_stream);
 }
 
 int halo_pack(const cav_grid* grid, const cav_halo* halo, const void* q, void* buf, size_t buf_bytes,

@@ -121,6 +121,17 @@ template <typename Real>
 hipError_t launch_nusselt(const Dims& d, const Bcs& b, CStateT<Real> q, double* out,
                           hipStream_t s);
 
+// Interior/exterior split of the sweep around the cuts of a virtual split:
+// P subdomains of extent e per axis; a cell within m of a cut is exterior;
+// exterior x and y slabs are cut into k chunks of kce planes.
+struct SplitGeom {
+    int P[3], e[3], m, kce;
+};
+int exterior_blocks(const Dims& d, const SweepGeom& g, const SplitGeom& sg);
+template <typename Real>
+hipError_t launch_split(const Dims& d, const Coef& c, const SweepGeom& g, const SplitGeom& sg, bool exterior,
+                        CStateT<Real> q, StateT<Real> qn, double* partials, bool with_norm, hipStream_t s);
+
 // Discrete adjoint (FP64): workspace size in doubles, one reverse step, and
 // the cotangent of the mean hot-wall Nusselt number (scale = ni/3/(nj nk dT)).
 size_t adjoint_ws_doubles(const Dims& d);

@@ -39,12 +39,41 @@ struct SweepLds {
     double red[TJ][NF];
 };
 
-// One tile: columns [i0, i0+64) x [j0, j0+8) of logical tile b, planes of
-// its k chunk.  Used by the single-cavity sweep and by the batched kernel.
-template <typename Real, bool NORM>
-__device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, int tiles_i, int tiles_j, int kc,
-                                           int b, const CStateT<Real>& q, const StateT<Real>& qn,
-                                           double* partials, SweepLds<Real>& L)
+// Where one block works: columns [i0, i0+64) x [j0, j0+8), planes
+// [k0, k1); its norm partial goes to slot pidx.
+struct TileBox {
+    int i0, j0, k0, k1, pidx;
+};
+
+// Logical tile b of the regular tiling with k chunks of length kc.
+__device__ __forceinline__ TileBox tile_box(const Dims& d, int tiles_i, int tiles_j, int kc, int b)
+{
+    const int bi = b % tiles_i;
+    const int bj = (b / tiles_i) % tiles_j;
+    const int bk = b / (tiles_i * tiles_j);
+    TileBox t;
+    t.i0 = bi * SW_TI;
+    t.j0 = bj * SW_TJ;
+    t.k0 = bk * kc;
+    t.k1 = min(t.k0 + kc, d.nk);
+    t.pidx = b;
+    return t;
+}
+
+// Every cell of the box is updated.  column(i, j): whether any updated cell
+// reads column (i, j).
+struct OwnAll {
+    __device__ __forceinline__ bool operator()(int, int, int) const { return true; }
+    __device__ __forceinline__ bool column(int, int) const { return true; }
+};
+
+// One tile box: planes of its k range, cells for which own(i, j, k) holds
+// are updated (and enter the norm).  Used by the single-cavity sweep, the
+// batched kernel and the interior/exterior split.
+template <typename Real, bool NORM, typename Own>
+__device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, const TileBox& tb, const Own& own,
+                                           const CStateT<Real>& q, const StateT<Real>& qn, double* partials,
+                                           SweepLds<Real>& L)
 {
     constexpr int TI = SW_TI, TJ = SW_TJ;
     constexpr int PW = SweepLds<Real>::PW, UW = SweepLds<Real>::UW;
@@ -52,16 +81,13 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
     Real* const sP = L.p;
     Real* const sU = L.u;
 
-    const int bi = b % tiles_i;
-    const int bj = (b / tiles_i) % tiles_j;
-    const int bk = b / (tiles_i * tiles_j);
-    const int i0 = bi * TI, j0 = bj * TJ;
-    const int k0 = bk * kc;
-    const int k1 = min(k0 + kc, d.nk);
+    const int i0 = tb.i0, j0 = tb.j0;
+    const int k0 = tb.k0, k1 = tb.k1;
 
     const int lane = threadIdx.x, row = threadIdx.y;
     const int i = i0 + lane, j = j0 + row;
-    const bool active = i < d.ni && j < d.nj;
+    // columns no owned cell's star reaches are neither loaded nor computed
+    const bool active = i < d.ni && j < d.nj && own.column(i, j);
 
     // New pressure at the centre cell, recomputed with the same arithmetic
     // as its owner, so that every block subtracts the identical value.
@@ -83,12 +109,12 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
     const bool has_prow = row < 4;
     const int prow_lds = row < 2 ? row : TJ + row;
     const int prow_j = j0 - 2 + prow_lds;
-    const bool ld_prow = has_prow && interior(i, prow_j);
+    const bool ld_prow = has_prow && interior(i, prow_j) && own.column(i, prow_j);
     // u v w T rows j0-1, j0+TJ: waves 0..7, field 1 + row/2
     const int urow_f = FU + (row >> 1);
     const int urow_lds = (row & 1) ? TJ + 1 : 0;
     const int urow_j = j0 - 1 + urow_lds;
-    const bool ld_urow = interior(i, urow_j);
+    const bool ld_urow = interior(i, urow_j) && own.column(i, urow_j);
     // column halos of this wave's row: lanes 0..3 p (i0-2, i0-1, i0+TI,
     // i0+TI+1), lanes 4..11 u v w T (i0-1, i0+TI)
     const bool has_col = lane < 12;
@@ -254,7 +280,7 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
             fix_ghosts(cP, cU, k);
             __syncthreads();
         }
-        if (active) {
+        if (active && own(i, j, k)) {
             Star<Real> s;
             s.p = p2;
             s.pxm = cP[lc_p - 1]; s.pxp = cP[lc_p + 1]; s.pxm2 = cP[lc_p - 2]; s.pxp2 = cP[lc_p + 2];
@@ -314,7 +340,7 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
             double t = 0.0;
 #pragma unroll
             for (int r = 0; r < TJ; ++r) t += red[r][lane];
-            partials[(size_t)b * NF + lane] = t;
+            partials[(size_t)tb.pidx * NF + lane] = t;
         }
     }
 }
@@ -328,7 +354,8 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef cd, S
     __shared__ SweepLds<Real> L;
     CoefR<Real> c = coef_as<Real>(cd);
     if constexpr (!FIELD) c.t_hot_field = nullptr;
-    sweep_tile<Real, NORM>(d, c, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks), q, qn, partials, L);
+    const TileBox tb = tile_box(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
+    sweep_tile<Real, NORM>(d, c, tb, OwnAll{}, q, qn, partials, L);
 }
 
 SweepGeom sweep_geom(const Dims& d, int slots)
@@ -385,6 +412,147 @@ template hipError_t launch_sweep<float>(const Dims&, const Coef&, const SweepGeo
                                         StateT<float>, double*, bool, hipStream_t);
 
 // ---------------------------------------------------------------------------
+// Interior/exterior split (Sec. 4.7): with a halo exchange in the step, the
+// cells whose stars reach no cell the unpack writes (the interior) are
+// updated by one launch that may run while the exchange is in flight; the
+// rest (the exterior: cells within `m` of a cut) by a second launch after
+// it.  Each cell is computed by exactly one launch with the same per-cell
+// code as the unsplit sweep, so the new state is bit-identical to it.
+
+// Cell x along `axis` lies within m of a cut between two subdomains.
+__device__ __forceinline__ bool near_cut(const SplitGeom& sg, int axis, int x)
+{
+    const int e = sg.e[axis];
+    const int a = x / e, local = x - a * e;
+    return (a > 0 && local < sg.m) || (a < sg.P[axis] - 1 && local >= e - sg.m);
+}
+
+struct OwnInterior {
+    SplitGeom sg;
+    __device__ __forceinline__ bool operator()(int i, int j, int k) const
+    {
+        return !(near_cut(sg, 0, i) || near_cut(sg, 1, j) || near_cut(sg, 2, k));
+    }
+    __device__ __forceinline__ bool column(int, int) const { return true; }
+};
+
+// The slab [cut - m, cut + m) along `axis`; cells also near a cut of a lower
+// axis belong to that axis's slab.
+struct OwnSlab {
+    SplitGeom sg;
+    int axis, cut;
+    __device__ __forceinline__ bool operator()(int i, int j, int k) const
+    {
+        const int x = axis == 0 ? i : (axis == 1 ? j : k);
+        if (x < cut - sg.m || x >= cut + sg.m) return false;
+        if (axis >= 1 && near_cut(sg, 0, i)) return false;
+        if (axis == 2 && near_cut(sg, 1, j)) return false;
+        return true;
+    }
+    // an x slab's cells read columns up to 2 cells beyond it
+    __device__ __forceinline__ bool column(int i, int) const
+    {
+        return axis != 0 || (i >= cut - sg.m - 2 && i < cut + sg.m + 2);
+    }
+};
+
+template <typename Real, bool NORM, bool FIELD>
+__global__ __launch_bounds__(SW_TI * SW_TJ) void interior_kernel(Dims d, Coef cd, SweepGeom g, SplitGeom sg,
+                                                                 CStateT<Real> q, StateT<Real> qn,
+                                                                 double* partials)
+{
+    __shared__ SweepLds<Real> L;
+    CoefR<Real> c = coef_as<Real>(cd);
+    if constexpr (!FIELD) c.t_hot_field = nullptr;
+    const TileBox tb = tile_box(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
+    sweep_tile<Real, NORM>(d, c, tb, OwnInterior{sg}, q, qn, partials, L);
+}
+
+// Exterior work items, block b: first the x slabs (per cut: j tiles x k
+// chunks of kce planes), then the y slabs (per cut: i tiles x k chunks),
+// then the z slabs (per cut: i x j tiles, the 2m planes around the cut).
+// Norm partials follow the interior launch's, at pidx = nblocks + b.
+template <typename Real, bool NORM, bool FIELD>
+__global__ __launch_bounds__(SW_TI * SW_TJ) void exterior_kernel(Dims d, Coef cd, SweepGeom g, SplitGeom sg,
+                                                                 CStateT<Real> q, StateT<Real> qn,
+                                                                 double* partials)
+{
+    __shared__ SweepLds<Real> L;
+    CoefR<Real> c = coef_as<Real>(cd);
+    if constexpr (!FIELD) c.t_hot_field = nullptr;
+    const int b = blockIdx.x;
+    const int nkce = (d.nk + sg.kce - 1) / sg.kce;
+    const int per0 = g.tiles_j * nkce, per1 = g.tiles_i * nkce, per2 = g.tiles_i * g.tiles_j;
+    const int n0 = (sg.P[0] - 1) * per0, n1 = (sg.P[1] - 1) * per1;
+    TileBox tb;
+    int axis, cut;
+    if (b < n0) {
+        axis = 0;
+        const int r = b % per0;
+        cut = (b / per0 + 1) * sg.e[0];
+        tb.i0 = cut - sg.m;
+        tb.j0 = (r % g.tiles_j) * SW_TJ;
+        tb.k0 = (r / g.tiles_j) * sg.kce;
+        tb.k1 = min(tb.k0 + sg.kce, d.nk);
+    } else if (b < n0 + n1) {
+        axis = 1;
+        const int r = (b - n0) % per1;
+        cut = ((b - n0) / per1 + 1) * sg.e[1];
+        tb.i0 = (r % g.tiles_i) * SW_TI;
+        tb.j0 = cut - sg.m;
+        tb.k0 = (r / g.tiles_i) * sg.kce;
+        tb.k1 = min(tb.k0 + sg.kce, d.nk);
+    } else {
+        axis = 2;
+        const int r = (b - n0 - n1) % per2;
+        cut = ((b - n0 - n1) / per2 + 1) * sg.e[2];
+        tb.i0 = (r % g.tiles_i) * SW_TI;
+        tb.j0 = (r / g.tiles_i) * SW_TJ;
+        tb.k0 = cut - sg.m;
+        tb.k1 = cut + sg.m;
+    }
+    tb.pidx = g.nblocks + b;
+    sweep_tile<Real, NORM>(d, c, tb, OwnSlab{sg, axis, cut}, q, qn, partials, L);
+}
+
+int exterior_blocks(const Dims& d, const SweepGeom& g, const SplitGeom& sg)
+{
+    const int nkce = (d.nk + sg.kce - 1) / sg.kce;
+    return (sg.P[0] - 1) * g.tiles_j * nkce + (sg.P[1] - 1) * g.tiles_i * nkce +
+           (sg.P[2] - 1) * g.tiles_i * g.tiles_j;
+}
+
+template <typename Real>
+hipError_t launch_split(const Dims& d, const Coef& c, const SweepGeom& g, const SplitGeom& sg, bool exterior,
+                        CStateT<Real> q, StateT<Real> qn, double* partials, bool with_norm, hipStream_t s)
+{
+    dim3 block(SW_TI, SW_TJ);
+    const int nb = exterior ? exterior_blocks(d, g, sg) : g.nblocks;
+    if (nb == 0) return hipSuccess;
+    const bool fld = c.t_hot_field != nullptr;
+#define SPLIT_LAUNCH(K)                                                                                  \
+    do {                                                                                                 \
+        if (fld) {                                                                                       \
+            if (with_norm) K<Real, true, true><<<nb, block, 0, s>>>(d, c, g, sg, q, qn, partials);        \
+            else K<Real, false, true><<<nb, block, 0, s>>>(d, c, g, sg, q, qn, partials);                 \
+        } else {                                                                                         \
+            if (with_norm) K<Real, true, false><<<nb, block, 0, s>>>(d, c, g, sg, q, qn, partials);       \
+            else K<Real, false, false><<<nb, block, 0, s>>>(d, c, g, sg, q, qn, partials);                \
+        }                                                                                                \
+    } while (0)
+    if (exterior)
+        SPLIT_LAUNCH(exterior_kernel);
+    else
+        SPLIT_LAUNCH(interior_kernel);
+#undef SPLIT_LAUNCH
+    return hipGetLastError();
+}
+template hipError_t launch_split<double>(const Dims&, const Coef&, const SweepGeom&, const SplitGeom&, bool,
+                                         CStateT<double>, StateT<double>, double*, bool, hipStream_t);
+template hipError_t launch_split<float>(const Dims&, const Coef&, const SweepGeom&, const SplitGeom&, bool,
+                                        CStateT<float>, StateT<float>, double*, bool, hipStream_t);
+
+// ---------------------------------------------------------------------------
 // Batched form: a persistent grid walks the work list of all members; each
 // item is one tile column's k chunk of one member, computed by the same
 // sweep_tile as the single-cavity sweep.  `parity` selects which of q and
@@ -409,7 +577,8 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void batch_kernel(const BatchCav* __
             qs.f[f] = cur + f * cv.fstride;
             qn.f[f] = nxt + f * cv.fstride;
         }
-        sweep_tile<Real, NORM>(d, c, cv.tiles_i, cv.tiles_j, cv.kc, w.tile, qs, qn, cv.ws + WS_HEAD_DOUBLES, L);
+        const TileBox tb = tile_box(d, cv.tiles_i, cv.tiles_j, cv.kc, w.tile);
+        sweep_tile<Real, NORM>(d, c, tb, OwnAll{}, qs, qn, cv.ws + WS_HEAD_DOUBLES, L);
         __syncthreads();                  // LDS is reused by the next item
     }
 }
