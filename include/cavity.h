@@ -239,8 +239,9 @@ int cavity_nusselt(const cav_grid* grid, const cav_params* prm, const void* q,
  * first).  q^n must be the states of the forward run (kept, or recomputed
  * from checkpoints); every call must get the same params as the forward. */
 
-/* Bytes of the workspace cavity_adjoint_step needs (8 + blocks + 41 values
- * per cell, in doubles); 0 for an invalid grid or a CAV_F32 grid. */
+/* Bytes of the workspace cavity_adjoint_step needs (in doubles: 8, the
+ * per-block partial sums, and 11 values per cell); 0 for an invalid grid or
+ * a CAV_F32 grid. */
 size_t cavity_adjoint_workspace_bytes(const cav_grid* grid);
 
 /* Cotangent of J = Nu(q): writes lam (device, state layout, interior cells;
@@ -258,7 +259,7 @@ int cavity_nusselt_adjoint(const cav_grid* grid, const cav_params* prm, void* la
  * step's terms into dj_dthot (device, nj*nk doubles, j fastest) and dj_dra
  * (device, 1 double); either may be NULL to skip it.  lam_out may equal
  * lam_in; neither may alias q_n.  ws: device, >=
- * cavity_adjoint_workspace_bytes.  Eight launches on `stream`, no
+ * cavity_adjoint_workspace_bytes.  Five launches on `stream`, no
  * allocation, no synchronisation.  CAV_EINVAL for a CAV_F32 grid. */
 int cavity_adjoint_step(const cav_grid* grid, const cav_params* prm,
                         const void* q_n, const void* lam_in, void* lam_out,

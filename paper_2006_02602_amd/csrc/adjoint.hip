@@ -9,19 +9,23 @@
 // cotangents of Theta and of Ra:
 //   1. lambda*_p(centre) = lambda_p(centre) - sum over cells of lambda_p
 //      (transpose of the rescale); lambda* = lambda elsewhere;
-//   2. per cell: seeds dR_f = lambda*_f dt, d(dt) = sum_f lambda*_f R_f,
-//      then the hand-written reverse of the residual gives the cotangents of
-//      the 41 star values (stored per cell and slot) and of nu, alpha and
-//      the viscous step limit (reduced per block into the Ra cotangent);
-//   3. per cell and face-ghost position: the sum of the star cotangents
-//      that land there, plus lambda* on interior cells (the identity part of
-//      q + dt R);
-//   4. transpose of the wall rules, one axis at a time: each ghost's
-//      cotangent moves onto the two interior cells (and Theta) it was
-//      derived from.
+//   2. record pass, per cell m (the forward sweep's k-marching tile, so the
+//      stars come from LDS and registers): seeds a_f = lambda*_f dt for R_f
+//      and b = sum_f lambda*_f R_f for dt, then the hand-written reverse of
+//      the residual.  The cotangents of m's 41 star values are linear in a
+//      few per-cell numbers -- a_u, a_v, a_w, a_T, eps4 a_p lambda_i/h_i
+//      (three), beta^2 a_p and the centre terms of u, v, w -- which are
+//      stored (11 doubles per cell); nu, alpha and the viscous step limit get
+//      their cotangents reduced per block into the Ra cotangent;
+//   3. gather pass, per cell e: lambda*(e) plus every star cotangent that
+//      lands on e, rebuilt from the records of the cells whose stars reach e
+//      (13 for p, 7 for u v w T) and their velocities; cells within two of a
+//      wall add the transposed wall rules of the ghosts their neighbours read
+//      (and the x = 0 wall rows add to dJ/dTheta).
 // Every sum runs in a fixed order, so results are run-to-run identical.
 #include "cavity_internal.h"
 #include "stencil.h"
+#include "sweep_tile.h"
 
 #include <algorithm>
 
@@ -29,84 +33,33 @@ namespace cav {
 
 namespace {
 
-constexpr int NSLOT = 41;          // 13 pressure + 4 x 7 star values
+constexpr int NREC = 11;           // record values per cell
 constexpr int ADJ_THREADS = 256;
+enum { R_XX, R_XY, R_XZ, R_BP, R_UB, R_VB, R_WB, R_AU, R_AV, R_AW, R_AT };
 
-// Star slot s of field f sits at offset (di, dj, dk) from its cell.
-struct SlotOff {
-    signed char f, di, dj, dk;
-};
-__constant__ SlotOff kSlots[NSLOT] = {
-    {FP, 0, 0, 0},  {FP, -1, 0, 0}, {FP, 1, 0, 0},  {FP, -2, 0, 0}, {FP, 2, 0, 0},  {FP, 0, -1, 0},
-    {FP, 0, 1, 0},  {FP, 0, -2, 0}, {FP, 0, 2, 0},  {FP, 0, 0, -1}, {FP, 0, 0, 1},  {FP, 0, 0, -2},
-    {FP, 0, 0, 2},
-    {FU, 0, 0, 0},  {FU, -1, 0, 0}, {FU, 1, 0, 0},  {FU, 0, -1, 0}, {FU, 0, 1, 0},  {FU, 0, 0, -1},
-    {FU, 0, 0, 1},
-    {FV, 0, 0, 0},  {FV, -1, 0, 0}, {FV, 1, 0, 0},  {FV, 0, -1, 0}, {FV, 0, 1, 0},  {FV, 0, 0, -1},
-    {FV, 0, 0, 1},
-    {FW, 0, 0, 0},  {FW, -1, 0, 0}, {FW, 1, 0, 0},  {FW, 0, -1, 0}, {FW, 0, 1, 0},  {FW, 0, 0, -1},
-    {FW, 0, 0, 1},
-    {FT, 0, 0, 0},  {FT, -1, 0, 0}, {FT, 1, 0, 0},  {FT, 0, -1, 0}, {FT, 0, 1, 0},  {FT, 0, 0, -1},
-    {FT, 0, 0, 1},
-};
-// first slot of each field and its count
-__device__ __forceinline__ int slot_begin(int f) { return f == FP ? 0 : 13 + 7 * (f - 1); }
-__device__ __forceinline__ int slot_count(int f) { return f == FP ? 13 : 7; }
-
-// Star values in slot order (the order of kSlots).
-__device__ __forceinline__ void star_to_slots(const Star<double>& s, double v[NSLOT])
-{
-    const double t[NSLOT] = {s.p,   s.pxm, s.pxp, s.pxm2, s.pxp2, s.pym, s.pyp, s.pym2, s.pyp2, s.pzm, s.pzp,
-                             s.pzm2, s.pzp2, s.u,  s.uxm,  s.uxp,  s.uym, s.uyp, s.uzm,  s.uzp,  s.v,   s.vxm,
-                             s.vxp, s.vym, s.vyp, s.vzm,  s.vzp,  s.w,   s.wxm, s.wxp,  s.wym,  s.wyp, s.wzm,
-                             s.wzp, s.t,   s.txm, s.txp,  s.tym,  s.typ, s.tzm, s.tzp};
-#pragma unroll
-    for (int i = 0; i < NSLOT; ++i) v[i] = t[i];
-}
-
-// Stars of interior cell (i, j, k) of q: direct loads two or more cells from
-// every wall, else the generic gather with the wall rules.
-__device__ __forceinline__ void gather_cell(const Dims& d, const CStateT<double>& q, const CoefR<double>& c,
-                                            int i, int j, int k, Star<double>& s)
-{
-    if (i < 2 || j < 2 || k < 2 || i >= d.ni - 2 || j >= d.nj - 2 || k >= d.nk - 2) {
-        gather_global(d, q, c, i, j, k, s);
-        return;
-    }
-    const int o = cell_off(d, i, j, k), X = 1, Y = d.sy, Z = d.sz;
-    const double* P = q.f[FP];
-    s.p = P[o];
-    s.pxm = P[o - X]; s.pxp = P[o + X]; s.pxm2 = P[o - 2 * X]; s.pxp2 = P[o + 2 * X];
-    s.pym = P[o - Y]; s.pyp = P[o + Y]; s.pym2 = P[o - 2 * Y]; s.pyp2 = P[o + 2 * Y];
-    s.pzm = P[o - Z]; s.pzp = P[o + Z]; s.pzm2 = P[o - 2 * Z]; s.pzp2 = P[o + 2 * Z];
-#define STAR7(F, nm)                                                              \
-    {                                                                             \
-        const double* A = q.f[F];                                                 \
-        s.nm = A[o];                                                              \
-        s.nm##xm = A[o - X]; s.nm##xp = A[o + X];                                 \
-        s.nm##ym = A[o - Y]; s.nm##yp = A[o + Y];                                 \
-        s.nm##zm = A[o - Z]; s.nm##zp = A[o + Z];                                 \
-    }
-    STAR7(FU, u) STAR7(FV, v) STAR7(FW, w) STAR7(FT, t)
-#undef STAR7
-}
-
-// Reverse of cell_residual: given the cotangents a[f] of R_f and b of dt,
-// return the cotangents of the 41 star values (in sb) and of nu, alpha and
-// the viscous step limit.  Non-smooth points take one side: |u| has slope
-// +1 at u = 0; beta^2 = max(|V|^2, floor) follows |V|^2 only where it is
-// strictly larger; dt follows the convective limit only where it is
-// strictly smaller than the viscous one.
-__device__ __forceinline__ void residual_reverse(const CoefR<double>& c, const Star<double>& s, const double a[NF],
-                                                 double b, Star<double>& sb, double& nub, double& alb,
-                                                 double& dtvb)
+// Reverse of cell_residual for one cell, reduced to its record: given the
+// cotangents a[f] of R_f and b of dt, every star cotangent of the cell is
+//   p:      centre -6 (Xx + Xy + Xz); at +-1 along x: -+a_u/(2h_x) + 4 Xx;
+//           at +-2 along x: -Xx (y, z alike with a_v, a_w)
+//   u:      centre ub + ctr nu a_u; at +-1 along x: -+(su a_u + Bp/(2h_x))
+//           + nu a_u/h_x^2; along y: -+sv a_u + nu a_u/h_y^2; z alike
+//   v, w:   likewise, with the Bp term along y for v and along z for w
+//   T:      centre a_w + ctr alpha a_T; along each axis -+s a_T + alpha a_T/h^2
+// with Xi = eps4 a_p lambda_i/h_i, Bp = beta^2 a_p, (su, sv, sw) = V/(2h),
+// ctr = -2 sum 1/h^2, "-+" meaning - at +1 and + at -1.  rec receives
+// Xx, Xy, Xz, Bp, ub, vb, wb, a_u, a_v, a_w, a_T; nub, alb, dtvb are the
+// cotangents of nu, alpha and the viscous step limit.  Non-smooth points
+// take one side: |u| has slope +1 at u = 0; beta^2 = max(|V|^2, floor)
+// follows |V|^2 only where strictly larger; dt follows the convective limit
+// only where strictly smaller than the viscous one.
+__device__ __forceinline__ void reverse_record(const CoefR<double>& c, const Star<double>& s, const double a[NF],
+                                               double b, double rec[NREC], double& nub, double& alb, double& dtvb)
 {
     // ---- forward intermediates (same formulas as cell_residual) ----
     const double dxu = s.uxp - s.uxm, dyu = s.uyp - s.uym, dzu = s.uzp - s.uzm;
     const double dxv = s.vxp - s.vxm, dyv = s.vyp - s.vym, dzv = s.vzp - s.vzm;
     const double dxw = s.wxp - s.wxm, dyw = s.wyp - s.wym, dzw = s.wzp - s.wzm;
     const double dxt = s.txp - s.txm, dyt = s.typ - s.tym, dzt = s.tzp - s.tzm;
-    const double su = s.u * c.hx2, sv = s.v * c.hy2, sw = s.w * c.hz2;
     const double u2 = s.u * s.u, v2 = s.v * s.v, w2 = s.w * s.w;
     const double vv = (u2 + v2) + w2;
     const bool beta_free = vv > c.beta2_floor;
@@ -122,32 +75,20 @@ __device__ __forceinline__ void residual_reverse(const CoefR<double>& c, const S
     const double fx = fma(6.0, s.p, fma(-4.0, s.pxp + s.pxm, s.pxp2 + s.pxm2));
     const double fy = fma(6.0, s.p, fma(-4.0, s.pyp + s.pym, s.pyp2 + s.pym2));
     const double fz = fma(6.0, s.p, fma(-4.0, s.pzp + s.pzm, s.pzp2 + s.pzm2));
-    const double lapu = lap3(c, s.u, s.uxm, s.uxp, s.uym, s.uyp, s.uzm, s.uzp);
-    const double lapv = lap3(c, s.v, s.vxm, s.vxp, s.vym, s.vyp, s.vzm, s.vzp);
-    const double lapw = lap3(c, s.w, s.wxm, s.wxp, s.wym, s.wyp, s.wzm, s.wzp);
-    const double lapt = lap3(c, s.t, s.txm, s.txp, s.tym, s.typ, s.tzm, s.tzp);
 
     // ---- reverse ----
-    // R_T = alpha lap T - adv T;  R_w = nu lap w + (T - t_inf) - (D_z p + adv w); ...
-    const double lapub = c.nu * a[FU], lapvb = c.nu * a[FV], lapwb = c.nu * a[FW], laptb = c.alpha * a[FT];
-    nub = (a[FU] * lapu + a[FV] * lapv) + a[FW] * lapw;
-    alb = a[FT] * lapt;
-    const double dxpb = -a[FU] * c.hx2, dypb = -a[FV] * c.hy2, dzpb = -a[FW] * c.hz2;
-    const double adub = -a[FU], advb = -a[FV], adwb = -a[FW], adtb = -a[FT];
+    nub = (a[FU] * lap3(c, s.u, s.uxm, s.uxp, s.uym, s.uyp, s.uzm, s.uzp) +
+           a[FV] * lap3(c, s.v, s.vxm, s.vxp, s.vym, s.vyp, s.vzm, s.vzp)) +
+          a[FW] * lap3(c, s.w, s.wxm, s.wxp, s.wym, s.wyp, s.wzm, s.wzp);
+    alb = a[FT] * lap3(c, s.t, s.txm, s.txp, s.tym, s.typ, s.tzm, s.tzp);
     // R_p = -beta^2 div - eps4 (lxn fx + lyn fy + lzn fz)
     double beta2b = -div * a[FP];
-    const double divb = -beta2 * a[FP];
     const double dissb = -c.eps4 * a[FP];
     double lxnb = fx * dissb, lynb = fy * dissb, lznb = fz * dissb;
-    const double fxb = lxn * dissb, fyb = lyn * dissb, fzb = lzn * dissb;
-    // advection: adv q = su D_x q + sv D_y q + sw D_z q (differences times 2h)
-    const double sub = ((adub * dxu + advb * dxv) + adwb * dxw) + adtb * dxt;
-    const double svb = ((adub * dyu + advb * dyv) + adwb * dyw) + adtb * dyt;
-    const double swb = ((adub * dzu + advb * dzv) + adwb * dzw) + adtb * dzt;
-    const double dxub = su * adub + c.hx2 * divb, dyub = sv * adub, dzub = sw * adub;
-    const double dxvb = su * advb, dyvb = sv * advb + c.hy2 * divb, dzvb = sw * advb;
-    const double dxwb = su * adwb, dywb = sv * adwb, dzwb = sw * adwb + c.hz2 * divb;
-    const double dxtb = su * adtb, dytb = sv * adtb, dztb = sw * adtb;
+    // advection (su D_x f + sv D_y f + sw D_z f) enters R_f with sign -
+    const double sub = -(((a[FU] * dxu + a[FV] * dxv) + a[FW] * dxw) + a[FT] * dxt);
+    const double svb = -(((a[FU] * dyu + a[FV] * dyv) + a[FW] * dyw) + a[FT] * dyt);
+    const double swb = -(((a[FU] * dzu + a[FV] * dzv) + a[FW] * dzw) + a[FT] * dzt);
     // dt = cfl min(1 / (lxn + lyn + lzn), dt_visc)
     dtvb = 0.0;
     if (convective) {
@@ -175,22 +116,17 @@ __device__ __forceinline__ void residual_reverse(const CoefR<double>& c, const S
     vb += 2.0 * s.v * v2b;
     wb += 2.0 * s.w * w2b;
 
-    const double ctr = -2.0 * ((c.ix2 + c.iy2) + c.iz2);
-    // pressure star: D p in the momentum equations, F p in the dissipation
-    sb.p = 6.0 * ((fxb + fyb) + fzb);
-    sb.pxp = dxpb - 4.0 * fxb; sb.pxm = -dxpb - 4.0 * fxb; sb.pxp2 = fxb; sb.pxm2 = fxb;
-    sb.pyp = dypb - 4.0 * fyb; sb.pym = -dypb - 4.0 * fyb; sb.pyp2 = fyb; sb.pym2 = fyb;
-    sb.pzp = dzpb - 4.0 * fzb; sb.pzm = -dzpb - 4.0 * fzb; sb.pzp2 = fzb; sb.pzm2 = fzb;
-#define STAR7B(nm, dxb, dyb, dzb, lb, cb)                                  \
-    sb.nm = (cb) + ctr * (lb);                                             \
-    sb.nm##xp = (dxb) + c.ix2 * (lb); sb.nm##xm = -(dxb) + c.ix2 * (lb);   \
-    sb.nm##yp = (dyb) + c.iy2 * (lb); sb.nm##ym = -(dyb) + c.iy2 * (lb);   \
-    sb.nm##zp = (dzb) + c.iz2 * (lb); sb.nm##zm = -(dzb) + c.iz2 * (lb);
-    STAR7B(u, dxub, dyub, dzub, lapub, ub)
-    STAR7B(v, dxvb, dyvb, dzvb, lapvb, vb)
-    STAR7B(w, dxwb, dywb, dzwb, lapwb, wb)
-    STAR7B(t, dxtb, dytb, dztb, laptb, a[FW])        // buoyancy: dR_w/dT = 1
-#undef STAR7B
+    rec[R_XX] = -lxn * dissb;
+    rec[R_XY] = -lyn * dissb;
+    rec[R_XZ] = -lzn * dissb;
+    rec[R_BP] = beta2 * a[FP];
+    rec[R_UB] = ub;
+    rec[R_VB] = vb;
+    rec[R_WB] = wb;
+    rec[R_AU] = a[FU];
+    rec[R_AV] = a[FV];
+    rec[R_AW] = a[FW];
+    rec[R_AT] = a[FT];
 }
 
 __device__ __forceinline__ int centre_off(const Dims& d) { return cell_off(d, d.ni / 2, d.nj / 2, d.nk / 2); }
@@ -219,14 +155,15 @@ __global__ __launch_bounds__(ADJ_THREADS) void row_sum_kernel(Dims d, const doub
     if (t == 0) part[blockIdx.x] = red[0];
 }
 
-// Sum of part[0..n) in a fixed order; out[0] = sum (or += when accumulate).
-__global__ __launch_bounds__(ADJ_THREADS) void sum_kernel(const double* __restrict__ part, int n, double* out,
-                                                          int accumulate)
+// Sum of part[b * stride] for b < n in a fixed order; out[0] = sum (or +=
+// when accumulate).
+__global__ __launch_bounds__(ADJ_THREADS) void sum_kernel(const double* __restrict__ part, int n, int stride,
+                                                          double* out, int accumulate)
 {
     __shared__ double red[ADJ_THREADS];
     const int t = threadIdx.x;
     double acc = 0.0;
-    for (int b = t; b < n; b += ADJ_THREADS) acc += part[b];
+    for (int b = t; b < n; b += ADJ_THREADS) acc += part[(size_t)b * stride];
     red[t] = acc;
     __syncthreads();
     for (int w = ADJ_THREADS / 2; w > 0; w >>= 1) {
@@ -236,141 +173,197 @@ __global__ __launch_bounds__(ADJ_THREADS) void sum_kernel(const double* __restri
     if (t == 0) out[0] = accumulate ? out[0] + red[0] : red[0];
 }
 
-// lambda* of interior cell offset o, field f (transpose of the rescale).
-__device__ __forceinline__ double lam_star(const Dims& d, const CStateT<double>& lam, int f, int o, double psum)
-{
-    const double v = lam.f[f][o];
-    return (f == FP && o == centre_off(d)) ? v - psum : v;
-}
-
-// ---- 2. per-cell reverse of the residual and the update ----
+// ---- 2. record pass ----
 struct RaFactors {
     double nu, alpha, dtv;        // d(nu)/dRa, d(alpha)/dRa, d(dt_visc)/dRa
 };
 
-__global__ __launch_bounds__(ADJ_THREADS) void cell_reverse_kernel(Dims d, Coef cd, RaFactors rf,
-                                                                   CStateT<double> q, CStateT<double> lam,
-                                                                   const double* __restrict__ psum,
-                                                                   double* __restrict__ T,
-                                                                   double* __restrict__ ra_part)
-{
-    __shared__ double red[ADJ_THREADS];
-    const CoefR<double> c = coef_as<double>(cd);
-    const long long n = (long long)d.ni * d.nj * d.nk;
-    const long long idx = (long long)blockIdx.x * ADJ_THREADS + threadIdx.x;
-    double ra = 0.0;
-    if (idx < n) {
-        const int i = (int)(idx % d.ni);
-        const long long r = idx / d.ni;
-        const int j = (int)(r % d.nj), k = (int)(r / d.nj);
-        Star<double> s;
-        gather_cell(d, q, c, i, j, k, s);
-        double R[NF], dt;
-        cell_residual(c, s, R, dt);
-        const int o = cell_off(d, i, j, k);
-        const double ps = psum[0];
+// What the k-marching tile does with each cell: seeds from lambda*, the
+// reverse of the residual, the record stored at the cell's dense index, the
+// Ra term into acc[0].
+struct RecordEpi {
+    CStateT<double> lam;
+    const double* psum;
+    double* rec;
+    long long n;
+    RaFactors rf;
+    double ps;
+    int centre;
+    __device__ __forceinline__ void prepare(const Dims& d, const CStateT<double>&, const CoefR<double>&)
+    {
+        ps = psum[0];
+        centre = centre_off(d);
+    }
+    __device__ __forceinline__ void cell(const CoefR<double>& c, const Star<double>& s, const double R[NF], double dt,
+                                         int o, int i, int j, int k, double acc[NF], const Dims& d)
+    {
         double a[NF], b = 0.0;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            const double ls = lam_star(d, lam, f, o, ps);
+            const double ls = (f == FP && o == centre) ? lam.f[f][o] - ps : lam.f[f][o];
             a[f] = ls * dt;
             b = fma(ls, R[f], b);
         }
-        Star<double> sb;
-        double nub, alb, dtvb;
-        residual_reverse(c, s, a, b, sb, nub, alb, dtvb);
-        double v[NSLOT];
-        star_to_slots(sb, v);
+        double v[NREC], nub, alb, dtvb;
+        reverse_record(c, s, a, b, v, nub, alb, dtvb);
+        const long long idx = i + (long long)d.ni * (j + (long long)d.nj * k);
 #pragma unroll
-        for (int sl = 0; sl < NSLOT; ++sl) T[(size_t)sl * n + idx] = v[sl];
-        ra = (nub * rf.nu + alb * rf.alpha) + dtvb * rf.dtv;
+        for (int m = 0; m < NREC; ++m) rec[(size_t)m * n + idx] = v[m];
+        acc[0] += (nub * rf.nu + alb * rf.alpha) + dtvb * rf.dtv;
     }
-    const int t = threadIdx.x;
-    red[t] = ra;
-    __syncthreads();
-    for (int w = ADJ_THREADS / 2; w > 0; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
+};
+
+// Binds the grid to RecordEpi::cell (the tile passes no grid to its
+// epilogue).
+struct RecordEpiD {
+    RecordEpi e;
+    Dims d;
+    __device__ __forceinline__ void prepare(const Dims& dd, const CStateT<double>& q, const CoefR<double>& c)
+    {
+        e.prepare(dd, q, c);
     }
-    if (t == 0) ra_part[blockIdx.x] = red[0];
+    __device__ __forceinline__ void cell(const CoefR<double>& c, const Star<double>& s, const double R[NF], double dt,
+                                         int o, int i, int j, int k, double acc[NF])
+    {
+        e.cell(c, s, R, dt, o, i, j, k, acc, d);
+    }
+};
+
+__global__ __launch_bounds__(SW_TI * SW_TJ) void record_kernel(Dims d, Coef cd, SweepGeom g, RaFactors rf,
+                                                               CStateT<double> q, CStateT<double> lam,
+                                                               const double* psum, double* rec, double* partials)
+{
+    __shared__ SweepLds<double> L;
+    const CoefR<double> c = coef_as<double>(cd);
+    const TileBox tb = tile_box(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
+    RecordEpiD epi{{lam, psum, rec, (long long)d.ni * d.nj * d.nk, rf, 0.0, 0}, d};
+    sweep_tile<double, true>(d, c, tb, OwnAll{}, q, epi, partials, L);
 }
 
-// ---- 3. gather of the star cotangents per cell and face-ghost position ----
-// One thread per position (i, j, k) of the box [-2, n+2)^3 of field
-// blockIdx.y; positions with two coordinates outside, or beyond the reach
-// of the field's star (2 for p, 1 for u v w T), are skipped.
-__global__ __launch_bounds__(ADJ_THREADS) void gather_kernel(Dims d, CStateT<double> lam,
-                                                             const double* __restrict__ psum,
-                                                             const double* __restrict__ T, StateT<double> out)
+// What the gather needs from a neighbour m one cell away along an axis:
+// the four velocity/temperature seeds, that axis's dissipation term and Bp,
+// and m's velocity along the axis times 1/(2h).
+struct Nb {
+    double au, av, aw, at, X, Bp, s;
+};
+
+// ---- 3. gather: lambda*(e) plus every star cotangent landing on e ----
+__global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coef cd, CStateT<double> q,
+                                                                     CStateT<double> lam,
+                                                                     const double* __restrict__ psum,
+                                                                     const double* __restrict__ rec,
+                                                                     StateT<double> out, double* __restrict__ dthot)
 {
-    const int f = blockIdx.y;
-    const int ei = d.ni + 2 * NG, ej = d.nj + 2 * NG, ek = d.nk + 2 * NG;
-    const long long e = (long long)blockIdx.x * ADJ_THREADS + threadIdx.x;
-    if (e >= (long long)ei * ej * ek) return;
-    const int i = (int)(e % ei) - NG;
-    const long long r = e / ei;
-    const int j = (int)(r % ej) - NG, k = (int)(r / ej) - NG;
-    const int reach = f == FP ? 2 : 1;
-    const int oi = i < 0 ? -i : (i >= d.ni ? i - d.ni + 1 : 0);
-    const int oj = j < 0 ? -j : (j >= d.nj ? j - d.nj + 1 : 0);
-    const int ok = k < 0 ? -k : (k >= d.nk ? k - d.nk + 1 : 0);
-    if ((oi > 0) + (oj > 0) + (ok > 0) > 1 || oi > reach || oj > reach || ok > reach) return;
+    const CoefR<double> c = coef_as<double>(cd);
     const long long n = (long long)d.ni * d.nj * d.nk;
-    double acc = 0.0;
-    const int s0 = slot_begin(f), ns = slot_count(f);
-    for (int sl = s0; sl < s0 + ns; ++sl) {
-        const SlotOff so = kSlots[sl];
-        const int mi = i - so.di, mj = j - so.dj, mk = k - so.dk;
-        if (mi >= 0 && mi < d.ni && mj >= 0 && mj < d.nj && mk >= 0 && mk < d.nk)
-            acc += T[(size_t)sl * n + mi + (long long)d.ni * (mj + (long long)d.nj * mk)];
-    }
+    const long long idx = (long long)blockIdx.x * ADJ_THREADS + threadIdx.x;
+    if (idx >= n) return;
+    const int i = (int)(idx % d.ni);
+    const long long r = idx / d.ni;
+    const int j = (int)(r % d.nj), k = (int)(r / d.nj);
     const int o = cell_off(d, i, j, k);
-    if (oi + oj + ok == 0) acc += lam_star(d, lam, f, o, psum[0]);
-    out.f[f][o] = acc;
-}
+    auto R = [&](int v, long long m) { return rec[(size_t)v * n + m]; };
+    const double ctr = -2.0 * ((c.ix2 + c.iy2) + c.iz2);
+    const double nu = c.nu, al = c.alpha;
 
-// ---- 4. transpose of the wall rules along one axis ----
-// Ghost g = 1, 2 beyond a wall was derived from interior cells m0 (next to
-// the wall) and m1:  p: g1 = 2 m0 - m1, g2 = 3 m0 - 2 m1;  u v w: g1 = -m0;
-// T: g1 = 2 T_wall - m0 (hot and cold walls), g1 = m0 (adiabatic).  One
-// thread per wall line handles both walls of the axis, low side first.
-__global__ __launch_bounds__(ADJ_THREADS) void wall_reverse_kernel(Dims d, int axis, StateT<double> lam,
-                                                                   double* __restrict__ dthot)
-{
-    const int n0 = axis == 0 ? d.nj : d.ni;            // tangential extents
-    const int n1 = axis == 2 ? d.nj : d.nk;
-    const long long t = (long long)blockIdx.x * ADJ_THREADS + threadIdx.x;
-    if (t >= (long long)n0 * n1) return;
-    const int a = (int)(t % n0), bq = (int)(t / n0);
-    const int nn = axis == 0 ? d.ni : (axis == 1 ? d.nj : d.nk);
-    const int stride = axis == 0 ? 1 : (axis == 1 ? d.sy : d.sz);
-    auto at = [&](int m) {                              // cell m along the axis
-        return axis == 0 ? cell_off(d, m, a, bq) : (axis == 1 ? cell_off(d, a, m, bq) : cell_off(d, a, bq, m));
-    };
-    for (int side = 0; side < 2; ++side) {
-        const int m0 = side ? at(nn - 1) : at(0);
-        const int s = side ? stride : -stride;          // towards the ghosts
-        const int m1 = m0 - s;
-        const int g1 = m0 + s, g2 = m0 + 2 * s;
-        {
-            double* L = lam.f[FP];
-            const double b1 = L[g1], b2 = L[g2];
-            L[m0] += 2.0 * b1 + 3.0 * b2;
-            L[m1] -= b1 + 2.0 * b2;
-        }
+    // own record, and lambda* (the identity part of q + dt R)
+    const double ps = psum[0];
+    const bool is_centre = o == centre_off(d);
+    const double Xe[3] = {R(R_XX, idx), R(R_XY, idx), R(R_XZ, idx)};
+    const double Bpe = R(R_BP, idx);
+    const double au = R(R_AU, idx), av = R(R_AV, idx), aw = R(R_AW, idx), at = R(R_AT, idx);
+    double Lp = (is_centre ? lam.f[FP][o] - ps : lam.f[FP][o]) - 6.0 * ((Xe[0] + Xe[1]) + Xe[2]);
+    double Lu = lam.f[FU][o] + (R(R_UB, idx) + ctr * nu * au);
+    double Lv = lam.f[FV][o] + (R(R_VB, idx) + ctr * nu * av);
+    double Lw = lam.f[FW][o] + (R(R_WB, idx) + ctr * nu * aw);
+    double Lt = lam.f[FT][o] + (aw + ctr * al * at);
+
+    const int pos[3] = {i, j, k};
+    const int N[3] = {d.ni, d.nj, d.nk};
+    const long long dstride[3] = {1, d.ni, (long long)d.ni * d.nj};
+    const int pstride[3] = {1, d.sy, d.sz};
+    const double h2[3] = {c.hx2, c.hy2, c.hz2};
+    const double i2[3] = {c.ix2, c.iy2, c.iz2};
 #pragma unroll
-        for (int f = FU; f <= FW; ++f) lam.f[f][m0] -= lam.f[f][g1];
-        {
-            double* L = lam.f[FT];
-            const double b1 = L[g1];
-            if (axis == 0) {
-                L[m0] -= b1;
-                if (side == 0 && dthot) dthot[a + (long long)d.nj * bq] += 2.0 * b1;
-            } else {
-                L[m0] += b1;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int x = pos[ax], nn = N[ax];
+        const double H = h2[ax], I2 = i2[ax];
+        const double* V = q.f[FU + ax];
+        auto nb = [&](int sgn) {
+            const long long m = idx + sgn * dstride[ax];
+            Nb b;
+            b.au = R(R_AU, m);
+            b.av = R(R_AV, m);
+            b.aw = R(R_AW, m);
+            b.at = R(R_AT, m);
+            b.X = R(R_XX + ax, m);
+            b.Bp = R(R_BP, m);
+            b.s = V[o + sgn * pstride[ax]] * H;
+            return b;
+        };
+        // the cotangents cell b's star puts on the cell one step from b in
+        // direction dir (+1: up the axis, slot "+"; -1: slot "-")
+        auto t7 = [&](const Nb& b, int dir, double& tu, double& tv, double& tw, double& tt, double& tp) {
+            const double sg = dir > 0 ? -1.0 : 1.0;
+            tp = sg * ((ax == 0 ? b.au : (ax == 1 ? b.av : b.aw)) * H) + 4.0 * b.X;
+            tu = sg * (b.s * b.au + (ax == 0 ? H * b.Bp : 0.0)) + I2 * nu * b.au;
+            tv = sg * (b.s * b.av + (ax == 1 ? H * b.Bp : 0.0)) + I2 * nu * b.av;
+            tw = sg * (b.s * b.aw + (ax == 2 ? H * b.Bp : 0.0)) + I2 * nu * b.aw;
+            tt = sg * (b.s * b.at) + I2 * al * b.at;
+        };
+        Nb lo{0, 0, 0, 0, 0, 0, 0}, hi{0, 0, 0, 0, 0, 0, 0};
+        double tu, tv, tw, tt, tp;
+        if (x > 0) {                      // the cell below reaches up to e
+            lo = nb(-1);
+            t7(lo, +1, tu, tv, tw, tt, tp);
+            Lp += tp; Lu += tu; Lv += tv; Lw += tw; Lt += tt;
+        }
+        if (x < nn - 1) {                 // the cell above reaches down to e
+            hi = nb(+1);
+            t7(hi, -1, tu, tv, tw, tt, tp);
+            Lp += tp; Lu += tu; Lv += tv; Lw += tw; Lt += tt;
+        }
+        if (x >= 2) Lp -= R(R_XX + ax, idx - 2 * dstride[ax]);
+        if (x < nn - 2) Lp -= R(R_XX + ax, idx + 2 * dstride[ax]);
+
+        // walls: ghosts g1, g2 beyond a wall carry the cotangents of the
+        // stars that read them; the wall rules move them onto m0 (next to
+        // the wall) and m1:  p: m0 += 2 g1 + 3 g2, m1 -= g1 + 2 g2;
+        // u v w: m0 -= g1;  T: m0 -= g1 on x walls (and Theta += 2 g1 at
+        // x = 0), m0 += g1 on the others.
+        if (x <= 1 || x >= nn - 2) {
+            const Nb me{au, av, aw, at, Xe[ax], Bpe, V[o] * H};
+            for (int side = 0; side < 2; ++side) {
+                const int dir = side ? +1 : -1;          // from m0 towards the wall
+                const int m0 = side ? nn - 1 : 0, m1 = side ? nn - 2 : 1;
+                if (x != m0 && x != m1) continue;
+                const Nb& B0 = x == m0 ? me : (side ? hi : lo);          // m0 seen from e
+                const double X1 = x == m1 ? Xe[ax] : (side ? lo.X : hi.X);   // m1's X
+                // g1 collects m0's one-step and m1's two-step reach past the
+                // wall, g2 m0's two-step reach
+                t7(B0, dir, tu, tv, tw, tt, tp);
+                const double g1p = tp - X1, g2p = -B0.X;
+                if (x == m0) {
+                    Lp += 2.0 * g1p + 3.0 * g2p;
+                    Lu -= tu;
+                    Lv -= tv;
+                    Lw -= tw;
+                    if (ax == 0) {
+                        Lt -= tt;
+                        if (side == 0 && dthot) dthot[j + (long long)d.nj * k] += 2.0 * tt;
+                    } else {
+                        Lt += tt;
+                    }
+                }
+                if (x == m1) Lp -= g1p + 2.0 * g2p;
             }
         }
     }
+    out.f[FP][o] = Lp;
+    out.f[FU][o] = Lu;
+    out.f[FV][o] = Lv;
+    out.f[FW][o] = Lw;
+    out.f[FT][o] = Lt;
 }
 
 // ---- cotangent of the mean hot-wall Nusselt number ----
@@ -392,6 +385,14 @@ __global__ __launch_bounds__(ADJ_THREADS) void nusselt_seed_kernel(Dims d, doubl
     if (i == 0 && dthot) dthot[j + (long long)d.nj * k] += 8.0 * scale;
 }
 
+// Partials of the record pass: one per block of any k-chunk tiling (the
+// chunking never yields more than nk/4 chunks per tile column), NF each.
+long long record_partials(const Dims& d)
+{
+    const long long tiles = (long long)((d.ni + SW_TI - 1) / SW_TI) * ((d.nj + SW_TJ - 1) / SW_TJ);
+    return tiles * std::max(1, d.nk / 4) * NF;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -399,52 +400,42 @@ size_t adjoint_ws_doubles(const Dims& d)
 {
     const long long n = (long long)d.ni * d.nj * d.nk;
     const long long rows = (long long)d.nj * d.nk;
-    const long long nb = std::max((n + ADJ_THREADS - 1) / ADJ_THREADS, (rows + ADJ_THREADS - 1) / ADJ_THREADS);
-    const long long part = (nb + 7) / 8 * 8;
-    return (size_t)(8 + part + (long long)NSLOT * n);
+    const long long part = std::max((rows + ADJ_THREADS - 1) / ADJ_THREADS, record_partials(d));
+    return (size_t)(8 + (part + 7) / 8 * 8 + (long long)NREC * n);
 }
 
-hipError_t launch_adjoint_step(const Dims& d, const Coef& c, double Ra, CStateT<double> q, CStateT<double> lam_in,
-                               StateT<double> lam_out, double* ws, double* dthot, double* dra, hipStream_t s)
+hipError_t launch_adjoint_step(const Dims& d, const Coef& c, const SweepGeom& g, double Ra, CStateT<double> q,
+                               CStateT<double> lam_in, StateT<double> lam_out, double* ws, double* dthot,
+                               double* dra, hipStream_t s)
 {
     const long long n = (long long)d.ni * d.nj * d.nk;
     const long long rows = (long long)d.nj * d.nk;
-    double* psum = ws;                       // ws[0]: sum of lambda_p; ws[1]: Ra scratch
+    double* psum = ws;                       // ws[0]: sum of lambda_p
     double* part = ws + 8;
-    const long long nb = std::max((n + ADJ_THREADS - 1) / ADJ_THREADS, (rows + ADJ_THREADS - 1) / ADJ_THREADS);
-    double* T = part + (nb + 7) / 8 * 8;
+    const long long np = std::max((rows + ADJ_THREADS - 1) / ADJ_THREADS, record_partials(d));
+    double* rec = part + (np + 7) / 8 * 8;
+    if ((long long)g.nblocks * NF > np) return hipErrorInvalidValue;
     hipError_t e;
 
     const int rb = (int)((rows + ADJ_THREADS - 1) / ADJ_THREADS);
     row_sum_kernel<<<rb, ADJ_THREADS, 0, s>>>(d, lam_in.f[FP], part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    sum_kernel<<<1, ADJ_THREADS, 0, s>>>(part, rb, psum, 0);
+    sum_kernel<<<1, ADJ_THREADS, 0, s>>>(part, rb, 1, psum, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
     RaFactors rf;
     rf.nu = -c.nu / (2.0 * Ra);
     rf.alpha = -c.alpha / (2.0 * Ra);
     rf.dtv = c.dt_visc / (2.0 * Ra);
-    const int cb = (int)((n + ADJ_THREADS - 1) / ADJ_THREADS);
-    cell_reverse_kernel<<<cb, ADJ_THREADS, 0, s>>>(d, c, rf, q, lam_in, psum, T, part);
+    record_kernel<<<g.nblocks, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, g, rf, q, lam_in, psum, rec, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (dra) {
-        sum_kernel<<<1, ADJ_THREADS, 0, s>>>(part, cb, dra, 1);
+        sum_kernel<<<1, ADJ_THREADS, 0, s>>>(part, g.nblocks, NF, dra, 1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-
-    const long long box = (long long)(d.ni + 2 * NG) * (d.nj + 2 * NG) * (d.nk + 2 * NG);
-    dim3 gg((unsigned)((box + ADJ_THREADS - 1) / ADJ_THREADS), NF);
-    gather_kernel<<<gg, ADJ_THREADS, 0, s>>>(d, lam_in, psum, T, lam_out);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-
-    const long long lines[3] = {(long long)d.nj * d.nk, (long long)d.ni * d.nk, (long long)d.ni * d.nj};
-    for (int axis = 0; axis < 3; ++axis) {
-        wall_reverse_kernel<<<(unsigned)((lines[axis] + ADJ_THREADS - 1) / ADJ_THREADS), ADJ_THREADS, 0, s>>>(
-            d, axis, lam_out, dthot);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    adjoint_gather_kernel<<<(unsigned)((n + ADJ_THREADS - 1) / ADJ_THREADS), ADJ_THREADS, 0, s>>>(
+        d, c, q, lam_in, psum, rec, lam_out, dthot);
+    return hipGetLastError();
 }
 
 hipError_t launch_nusselt_seed(const Dims& d, double scale, StateT<double> lam, double* dthot, hipStream_t s)

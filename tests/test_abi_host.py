@@ -131,9 +131,12 @@ def test_adjoint_validation():
     L = C.lib()
     g64, g32 = C.Grid(16, 12, 10), C.Grid(16, 12, 10, dtype=C.CAV_F32)
     need = C.cavity_adjoint_workspace_bytes(g64)
-    # 8 head doubles + per-block partials (rounded to 8) + 41 values per cell
-    nb = max(-(-16 * 12 * 10 // 256), -(-12 * 10 // 256))
-    assert need == 8 * (8 + -(-nb // 8) * 8 + 41 * 16 * 12 * 10)
+    # 8 head doubles + partials (rounded to 8: 5 per record-pass block, at
+    # most tiles * max(1, nk/4) blocks; or one per 256 rows) + an 11-value
+    # record per cell
+    tiles = 1 * 2
+    nb = max(-(-12 * 10 // 256), tiles * max(1, 10 // 4) * 5)
+    assert need == 8 * (8 + -(-nb // 8) * 8 + 11 * 16 * 12 * 10)
     assert C.cavity_adjoint_workspace_bytes(g32) == 0
     G, P = ctypes.byref(g64.c()), ctypes.byref(C.Params().c())
     a, b = FAKE, ctypes.c_void_p(FAKE.value + 4096)
