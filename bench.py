@@ -34,7 +34,7 @@ def log(*a):
 
 def sweep_source_hash():
     h = hashlib.sha256()
-    for f in ("sweep.hip", "cavity_internal.h"):
+    for f in ("sweep.hip", "sweep_tile.h", "stencil.h", "cavity_internal.h"):
         with open(os.path.join(ROOT, "paper_2006_02602_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -286,10 +286,23 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the discrete-adjoint leg")
     ap.add_argument("--no-overlap", action="store_true", help="skip the interior/exterior split leg")
+    ap.add_argument("--legs", default=None,
+                    help="comma list of extra legs to run (halo,f32,batch,adjoint,overlap; 'none' for the "
+                         "headline only); overrides the --no-* flags")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.legs is not None:
+        want = set(x.strip() for x in args.legs.split(",") if x.strip())
+        unknown = want - {"none", "halo", "f32", "batch", "adjoint", "overlap"}
+        if unknown:
+            ap.error("unknown legs: %s" % ",".join(sorted(unknown)))
+        args.no_halo_bench = "halo" not in want
+        args.no_f32 = "f32" not in want
+        args.no_batch = "batch" not in want
+        args.no_adjoint = "adjoint" not in want
+        args.no_overlap = "overlap" not in want
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU's share of the cavity; it does not run on %d GPUs "

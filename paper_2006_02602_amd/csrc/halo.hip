@@ -7,32 +7,18 @@
 // blockIdx.y = subdomain * 6 + face, blockIdx.x walks the face's tangential
 // cells.  Each thread owns one tangential cell of the face and moves all
 // fields and layers of it, so the buffer position needs one integer
-// division per thread.  The buffer offset of a subdomain is a closed-form
-// prefix sum over the cut faces that precede it.
-//
-// Buffer layout: subdomains s = a + Pi*(b + Pj*c) in order; faces
-// -x, +x, -y, +y, -z, +z that are cuts; fields p, u, v, w, T with width > 0;
-// within a field the sender's box in (k, j, i) order, i fastest.
+// division per thread.  The buffer layout is in halo_layout.h.
 #include "cavity_internal.h"
+#include "halo_layout.h"
 
 namespace cav {
-
-// Cut faces along one axis among the first m of P subdomains.
-__device__ __forceinline__ long long cuts_before(int P, int m)
-{
-    return m == 0 ? 0 : (long long)(m - 1) + min(m, P - 1);
-}
-__device__ __forceinline__ int cuts_of(int P, int a)
-{
-    return (a > 0 ? 1 : 0) + (a < P - 1 ? 1 : 0);
-}
 
 template <typename Real, bool PACK>
 __global__ __launch_bounds__(256) void halo_kernel(Dims d, HaloGeom h, StateT<Real> q, Real* buf)
 {
     const int slot = blockIdx.y;
     const int s = slot / 6, face = slot - 6 * s;
-    const int Pi = h.P[0], Pj = h.P[1], Pk = h.P[2];
+    const int Pi = h.P[0], Pj = h.P[1];
     const int a = s % Pi, c = s / (Pi * Pj), b = (s / Pi) % Pj;
     const int axis = face >> 1;
     const bool high = face & 1;
@@ -43,20 +29,8 @@ __global__ __launch_bounds__(256) void halo_kernel(Dims d, HaloGeom h, StateT<Re
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= area) return;
 
-    // offset (in tangential cells) of subdomain s, then of this face within s
-    const long long Ax = h.area[0], Ay = h.area[1], Az = h.area[2];
-    long long u = (long long)c * (Ax * 2LL * (Pi - 1) * Pj + Ay * 2LL * (Pj - 1) * Pi)
-                + Az * cuts_before(Pk, c) * Pi * Pj
-                + (long long)b * Ax * 2LL * (Pi - 1) + Ay * cuts_before(Pj, b) * Pi
-                + Az * cuts_of(Pk, c) * (long long)Pi * b
-                + Ax * cuts_before(Pi, a) + Ay * cuts_of(Pj, b) * (long long)a
-                + Az * cuts_of(Pk, c) * (long long)a;
-    const int cc[3] = {a, b, c};
-    for (int f2 = 0; f2 < face; ++f2) {
-        const int ax2 = f2 >> 1;
-        const bool hi2 = f2 & 1;
-        if (!(hi2 ? cc[ax2] == h.P[ax2] - 1 : cc[ax2] == 0)) u += h.area[ax2];
-    }
+    // offset (in tangential cells) of this face's segment
+    const long long u = face_offset(h, a, b, c, face);
     Real* __restrict__ B = buf + u * h.wsum;
 
     // this thread's tangential cell, the first layer's offset per field and
