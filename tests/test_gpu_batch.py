@@ -126,3 +126,22 @@ def test_autotuner_returns_valid_choices(C):
     b = C.Batch([(C.Grid.cube(e, 1), C.Params(), kcs[e]) for e in (24, 32, 32)]).init([1, 2, 3])
     nb, t = autotune.tune_blocks(b, steps=2, reps=1)
     assert nb in autotune.BLOCK_CANDIDATES and len(t) == len(autotune.BLOCK_CANDIDATES)
+
+
+def test_batch_member_with_hot_wall_field(C):
+    """A member whose hot wall is a per-row field advances bit-identically to
+    the same cavity alone (the work items carry the member's field)."""
+    import torch
+    say("batch wall field")
+    n = (40, 24, 18)
+    theta = torch.from_numpy(1.0 + 0.05 * np.random.default_rng(8).uniform(-1, 1, n[1] * n[2])).cuda()
+    prm = C.Params(Ra=1e5, t_hot_field=theta)
+    b = C.Batch([(C.Grid(*n), prm), (C.Grid(16, 16, 16), C.Params(Ra=1e3))]).init([5, 6])
+    b.step(7)
+    cav = C.Cavity(C.Grid(*n), prm).init(5)
+    cav.step(7)
+    g = C.Grid(*n)
+    assert np.array_equal(interior(C, g, b.state(0)), interior(C, g, cav.q))
+    uniform = C.Cavity(C.Grid(*n), C.Params(Ra=1e5)).init(5)
+    uniform.step(7)
+    assert not np.array_equal(interior(C, g, uniform.q), interior(C, g, cav.q))

@@ -114,3 +114,21 @@ def test_tangent_is_linear_in_the_direction():
     _, c = TG.nusselt_tangent(*n, 1e5, theta, q0, 5, dRa=3e4)
     _, abc = TG.nusselt_tangent(*n, 1e5, theta, q0, 5, dq=dq, dtheta=dth, dRa=3e4)
     assert abc == pytest.approx(a + b + c, rel=1e-12, abs=1e-14)
+
+
+def test_planted_mistake_in_the_tangent_is_caught(monkeypatch):
+    """A complex-step derivative is exact for the function as written, so a
+    wrong derivative needs a non-analytic operation done wrong: np.abs on a
+    complex number returns a real magnitude and drops the imaginary part.
+    Planted in the oracle's |.|, the comparison with finite differences of
+    the C oracle fails while the real part still agrees."""
+    n, Ra, steps = (8, 8, 8), 1e6, 8
+    q0, theta = start(n, 21)
+    dq, _ = _directions(n, 22)
+    eps = 1e-7
+    fd = (c_oracle_nu(n, Ra, theta, q0 + eps * dq, steps)[0] - c_oracle_nu(n, Ra, theta, q0 - eps * dq, steps)[0]) / (2 * eps)
+    monkeypatch.setattr(TG, "_abs", lambda z: np.abs(z) + 0j)
+    J, dJ = TG.nusselt_tangent(*n, Ra, theta, q0, steps, dq=dq)
+    J0 = c_oracle_nu(n, Ra, theta, q0, steps)[0]
+    assert abs(J - J0) <= 1e-12 * abs(J0)
+    assert abs(dJ - fd) > 1e-4 * abs(fd)
