@@ -132,19 +132,20 @@ __device__ __forceinline__ void reverse_record(const CoefR<double>& c, const Sta
 __device__ __forceinline__ int centre_off(const Dims& d) { return cell_off(d, d.ni / 2, d.nj / 2, d.nk / 2); }
 
 // ---- 1. sum of lambda_p over the interior, fixed order ----
-// Stage 1: one thread per (j, k) row, summing along i; a fixed tree per
-// block writes part[block].
-__global__ __launch_bounds__(ADJ_THREADS) void row_sum_kernel(Dims d, const double* __restrict__ lp,
+// Stage 1: block b sums the interior cells of rows [b*rpb, (b+1)*rpb) (row
+// = (j, k)), the threads striding over the group's cells with i fastest so
+// that loads are coalesced; a fixed tree per block writes part[b].
+__global__ __launch_bounds__(ADJ_THREADS) void row_sum_kernel(Dims d, int rpb, const double* __restrict__ lp,
                                                               double* __restrict__ part)
 {
     __shared__ double red[ADJ_THREADS];
     const int t = threadIdx.x;
-    const long long r = (long long)blockIdx.x * ADJ_THREADS + t;
+    const int rows = d.nj * d.nk;
+    const int r0 = blockIdx.x * rpb, r1 = min(r0 + rpb, rows);
     double acc = 0.0;
-    if (r < (long long)d.nj * d.nk) {
-        const int j = (int)(r % d.nj), k = (int)(r / d.nj);
-        const int o = cell_off(d, 0, j, k);
-        for (int i = 0; i < d.ni; ++i) acc += lp[o + i];
+    for (int r = r0; r < r1; ++r) {                      // uniform: row offsets in scalar registers
+        const int o = cell_off(d, 0, r % d.nj, r / d.nj);
+        for (int i = t; i < d.ni; i += ADJ_THREADS) acc += lp[o + i];
     }
     red[t] = acc;
     __syncthreads();
@@ -400,7 +401,7 @@ size_t adjoint_ws_doubles(const Dims& d)
 {
     const long long n = (long long)d.ni * d.nj * d.nk;
     const long long rows = (long long)d.nj * d.nk;
-    const long long part = std::max((rows + ADJ_THREADS - 1) / ADJ_THREADS, record_partials(d));
+    const long long part = std::max(std::min(rows, 1024LL), record_partials(d));
     return (size_t)(8 + (part + 7) / 8 * 8 + (long long)NREC * n);
 }
 
@@ -412,13 +413,16 @@ hipError_t launch_adjoint_step(const Dims& d, const Coef& c, const SweepGeom& g,
     const long long rows = (long long)d.nj * d.nk;
     double* psum = ws;                       // ws[0]: sum of lambda_p
     double* part = ws + 8;
-    const long long np = std::max((rows + ADJ_THREADS - 1) / ADJ_THREADS, record_partials(d));
+    const long long np = std::max(std::min(rows, 1024LL), record_partials(d));
     double* rec = part + (np + 7) / 8 * 8;
     if ((long long)g.nblocks * NF > np) return hipErrorInvalidValue;
+    // about 1024 blocks of whole rows, at most one per partial slot
+    const int rpb = (int)std::max(1LL, (rows + 1023) / 1024);
+    const int rb = (int)((rows + rpb - 1) / rpb);
+    if (rb > np) return hipErrorInvalidValue;
     hipError_t e;
 
-    const int rb = (int)((rows + ADJ_THREADS - 1) / ADJ_THREADS);
-    row_sum_kernel<<<rb, ADJ_THREADS, 0, s>>>(d, lam_in.f[FP], part);
+    row_sum_kernel<<<rb, ADJ_THREADS, 0, s>>>(d, rpb, lam_in.f[FP], part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     sum_kernel<<<1, ADJ_THREADS, 0, s>>>(part, rb, 1, psum, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -138,3 +138,44 @@ def test_unpack_round_trip_and_poison(orc, split, width):
     q[mark == 1] = np.nan
     O.halo_unpack(P, halo, buf, q)
     assert np.array_equal(q, q0)
+
+
+# ---------------------------------------------------------------------------
+# Widths against the stencil reach (Sec. 3.1: p reads 2 cells, u v w T 1).
+# With really separate subdomains a receiver sees only the w_f layers the
+# exchange sent; whatever lies beyond them is stale.  Marking those cells NaN
+# in the global array and evaluating the residual of one subdomain shows
+# which widths suffice: the paper's stencil widths (p 2, others 1)
+# reproduce the global residual exactly, while p = 1 (the widths of the
+# single-array timed runs) or a zero width do not.
+def _residual_seen_by(n, split_axis, w, seed=5):
+    from oracle import tangent as TG
+    ni, nj, nk = n
+    P = O.Problem(ni, nj, nk, Ra=1e5)
+    q = O.init(P, seed, 1e-2)
+    C = TG.Case(ni, nj, nk, 1e5, np.full(nj * nk, 1.0))
+    g = q.copy()
+    TG.apply_bc(C, g)
+    R_ref, _ = TG.residual(C, g)
+    e = (ni, nj, nk)[split_axis] // 2          # one cut, at e
+    seen = g.copy()
+    for f in range(5):
+        idx = [f, slice(None), slice(None), slice(None)]
+        idx[3 - split_axis] = slice(O.NG + e + w[f], None)   # beyond the width, on the far side
+        seen[tuple(idx)] = np.nan
+    R, _ = TG.residual(C, seen)
+    near = [slice(None), slice(None), slice(None), slice(None)]
+    near[3 - split_axis] = slice(0, e)                          # the subdomain below the cut
+    return R[tuple(near)], R_ref[tuple(near)]
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_stencil_widths_suffice_for_separate_subdomains(axis):
+    got, ref = _residual_seen_by((12, 10, 8), axis, (2, 1, 1, 1, 1))
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("w", [(1, 2, 2, 2, 2), (2, 0, 1, 1, 1), (2, 1, 1, 1, 0)])
+def test_narrower_widths_break_separate_subdomains(w):
+    got, ref = _residual_seen_by((12, 10, 8), 0, w)
+    assert not np.isfinite(got).all()
