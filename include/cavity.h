@@ -10,7 +10,11 @@
  *     rescale at the cavity centre (Sec. 2),
  *   - in-device packing / unpacking of noncontiguous halo faces into one
  *     contiguous buffer with a ghost width per variable (Sec. 4.5,
- *     "Optimized V1/V2/V3", Listings 1-2).
+ *     "Optimized V1/V2/V3", Listings 1-2),
+ * and around them: an FP32 precision form, a batched form (many cavities,
+ * one launch per step, graph replay), the interior/exterior split step of
+ * Sec. 4.7 (the exchange on a second stream), and the discrete adjoint of
+ * the step and of the hot-wall Nusselt number.
  *
  * Conventions shared by every call
  *   - State layout.  q is ONE allocation of 5 fields in the order
@@ -25,14 +29,15 @@
  *     sj = (lead + ni + 2) rounded up to a multiple of lead,
  *     sk = (nj+4)*sj, sf = (nk+4)*sk (cavity_layout returns them).  Interior
  *     cells are 0 <= i < ni etc.  cavity_init also fills the face ghost
- *     layers; cavity_step never reads a ghost cell (their contents after a
- *     step are unspecified).  Element type: double for CAV_F64, float for
+ *     layers; no step reads a ghost cell (their contents after a step are
+ *     unspecified).  Element type: double for CAV_F64, float for
  *     CAV_F32 (the halo buffer uses the same element type).
  *   - Pointers are DEVICE pointers unless the comment says (host).  The
  *     caller owns every buffer; the library allocates no device memory and
  *     keeps no pointer after a call returns.
  *   - Every call enqueues its work on `stream` (0 = the null stream) and
- *     returns without waiting, except cavity_residual_norm, which waits.
+ *     returns without waiting, except cavity_residual_norm, cavity_nusselt,
+ *     cavity_batch_build and cavity_timing_read, which wait (each says so).
  *   - Arguments are validated on the host BEFORE anything is enqueued; on
  *     any error nothing is enqueued and a negative CAV_E* code is returned.
  *     cavity_last_error() then describes the failure (thread-local text).

@@ -1,5 +1,8 @@
-// Residual + Euler-update sweep, wall boundary conditions, seeded init and
-// the residual-norm finalize for gfx950 (FP64).
+// Residual + Euler-update sweep kernels (single cavity, interior/exterior
+// split, batched), wall boundary conditions, seeded init, the hot-wall
+// Nusselt integral and the residual-norm finalize for gfx950, in FP64 and
+// FP32 (the per-cell code is in stencil.h, the k-marching tile in
+// sweep_tile.h).
 //
 // The method (Xue & Roy, arXiv:2006.02602): artificial-compressibility
 // Boussinesq equations (Sec. 2, Eq. 1-3), second-order central differences
