@@ -288,13 +288,6 @@ int check_batch(const cav_batch* b)
     return CAV_OK;
 }
 
-int default_blocks()
-{
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    return cus > 0 ? cus : 256;
-}
-
 int do_halo(const cav_grid* grid, const HaloGeom& hg, void* q, void* buf, bool pack, hipStream_t s)
 {
     if (hg.face_blocks == 0 || hg.wsum == 0) return CAV_OK;       // nothing to exchange
@@ -394,12 +387,12 @@ int overlap_impl(const cav_grid* grid, const cav_params* prm, const HaloGeom& hg
     hipError_t e;
     if ((e = hipEventCreateWithFlags(&ready, hipEventDisableTiming)) != hipSuccess) return hip_fail("event create", e);
     if ((e = hipEventCreateWithFlags(&exchanged, hipEventDisableTiming)) != hipSuccess) {
-        hipEventDestroy(ready);
+        (void)hipEventDestroy(ready);
         return hip_fail("event create", e);
     }
-    auto done = [&](int r) {
-        hipEventDestroy(ready);
-        hipEventDestroy(exchanged);
+    auto done = [&](int r) {                             // destroyed once their work completes
+        (void)hipEventDestroy(ready);
+        (void)hipEventDestroy(exchanged);
         return r;
     };
     void* cur = q;
@@ -730,7 +723,7 @@ int cavity_batch_step(cav_batch* batch, int32_t nsteps, int32_t nblocks, hipStre
     if (nsteps < 0) return fail(CAV_EINVAL, "nsteps = %d must be >= 0", nsteps);
     if (nblocks < 0) return fail(CAV_EINVAL, "nblocks = %d must be >= 0", nblocks);
     if (nsteps == 0) return CAV_OK;
-    const int nb = nblocks ? nblocks : default_blocks();
+    const int nb = nblocks ? nblocks : device_slots();
     const hipError_t e = batch->dtype == CAV_F32 ? batch_launches<float>(*batch, nsteps, nb, batch->parity, stream, true)
                                                  : batch_launches<double>(*batch, nsteps, nb, batch->parity, stream, true);
     if (e != hipSuccess) return hip_fail("batch launch", e);
@@ -747,7 +740,7 @@ int cavity_batch_graph_create(const cav_batch* batch, int32_t nsteps, int32_t nb
     if (nblocks < 0) return fail(CAV_EINVAL, "nblocks = %d must be >= 0", nblocks);
     if (!graph_exec) return fail(CAV_EINVAL, "graph_exec is NULL");
     if (!stream) return fail(CAV_EINVAL, "graph capture needs a created stream, not the null stream");
-    const int nb = nblocks ? nblocks : default_blocks();
+    const int nb = nblocks ? nblocks : device_slots();
     hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail("begin capture", e);
     hipError_t el = batch->dtype == CAV_F32 ? batch_launches<float>(*batch, nsteps, nb, batch->parity, stream, false)
@@ -755,12 +748,12 @@ int cavity_batch_graph_create(const cav_batch* batch, int32_t nsteps, int32_t nb
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(stream, &graph);
     if (el != hipSuccess || e != hipSuccess) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return hip_fail("batch capture", el != hipSuccess ? el : e);
     }
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return hip_fail("graph instantiate", e);
     *graph_exec = exec;
     return CAV_OK;
