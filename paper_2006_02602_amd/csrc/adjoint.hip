@@ -238,7 +238,7 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void record_kernel(Dims d, Coef cd, 
     const CoefR<double> c = coef_as<double>(cd);
     const TileBox tb = tile_box(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
     RecordEpiD epi{{lam, psum, rec, (long long)d.ni * d.nj * d.nk, rf, 0.0, 0}, d};
-    sweep_tile<double, true>(d, c, tb, OwnAll{}, q, epi, partials, L);
+    sweep_tile<double, true, OwnAll, RecordEpiD, 2>(d, c, tb, OwnAll{}, q, epi, partials, L);
 }
 
 // What the gather needs from a neighbour m one cell away along an axis:

@@ -257,7 +257,7 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void batch_kernel(const BatchCav* __
         }
         const TileBox tb = tile_box(d, cv.tiles_i, cv.tiles_j, cv.kc, w.tile);
         StepEpi<Real> epi{qn, Real(0)};
-        sweep_tile<Real, NORM>(d, c, tb, OwnAll{}, qs, epi, cv.ws + WS_HEAD_DOUBLES, L);
+        sweep_tile<Real, NORM, OwnAll, StepEpi<Real>, 2>(d, c, tb, OwnAll{}, qs, epi, cv.ws + WS_HEAD_DOUBLES, L);
         __syncthreads();                  // LDS is reused by the next item
     }
 }

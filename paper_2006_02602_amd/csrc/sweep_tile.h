@@ -15,7 +15,7 @@ namespace cav {
 // the k neighbours come from per-thread register queues (p: k-2..k+2,
 // others k-1..k+1).  The LDS planes are double-buffered: plane k+1 is
 // written into one buffer while plane k is computed from the other, so each
-// plane costs one barrier; global loads run two planes ahead.  Wall ghosts
+// plane costs one barrier; global loads run two or three planes ahead.  Wall ghosts
 // are derived from interior cells (in LDS for the i/j walls, by recurrences
 // on the queues for the k walls); no ghost cell is read from HBM.
 // LDS of one sweep block: two planes of p (halo 2) and of u, v, w, T
@@ -94,7 +94,7 @@ struct OwnAll {
 // One tile box: planes of its k range, cells for which own(i, j, k) holds
 // are updated (and enter the norm).  Used by the single-cavity sweep, the
 // batched kernel and the interior/exterior split.
-template <typename Real, bool NORM, typename Own, typename Epi>
+template <typename Real, bool NORM, typename Own, typename Epi, int DEPTH = 3>
 __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, const TileBox& tb, const Own& own,
                                            const CStateT<Real>& q, Epi& epi, double* partials, SweepLds<Real>& L)
 {
@@ -237,9 +237,10 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
     sU[urow_dst] = ld_urow ? URg[off_urow + k0 * Z] : Real(0);
     if (has_col) (col_f == FP ? sP : sU)[col_lds] = ld_col ? COLg[off_col + k0 * Z] : Real(0);
 
-    // Loads run two planes ahead: what the iteration for plane k needs from
-    // memory (queue heads p(k+2), uvwT(k+1), halo strips of plane k+1) is
-    // issued while plane k-2 is computed.  Two register sets alternate.
+    // Loads run DEPTH planes ahead: what the iteration for plane k needs
+    // from memory (queue heads p(k+2), uvwT(k+1), halo strips of plane k+1)
+    // is issued while plane k-DEPTH is computed; DEPTH register sets rotate
+    // (3 for the step kernels; 2 where the epilogue needs the registers).
     struct InFlight {
         Real p, u, v, w, t, prow, urow, col;
     };
@@ -259,9 +260,12 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
             if (ld_col) F.col = COLg[off_col + (k + 1) * Z];
         }
     };
-    InFlight X{0, 0, 0, 0, 0, 0, 0, 0}, Y{0, 0, 0, 0, 0, 0, 0, 0};
+    static_assert(DEPTH == 2 || DEPTH == 3, "prefetch depth is 2 or 3 planes");
+    InFlight X{0, 0, 0, 0, 0, 0, 0, 0}, Y{0, 0, 0, 0, 0, 0, 0, 0}, Zs{0, 0, 0, 0, 0, 0, 0, 0};
     issue(X, k0);
     if (k0 + 1 < k1) issue(Y, k0 + 1);
+    if constexpr (DEPTH == 3)
+        if (k0 + 2 < k1) issue(Zs, k0 + 2);
     __syncthreads();
 
     double acc[NF] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -286,7 +290,7 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
             nU[urow_dst] = F.urow;
             if (has_col) (col_f == FP ? nP : nU)[col_lds] = F.col;
         }
-        if (k + 2 < k1) issue(F, k + 2);
+        if (k + DEPTH < k1) issue(F, k + DEPTH);
 
         Real* const cP = sP + buf * PPL;
         Real* const cU = sU + buf * 4 * UPL;
@@ -319,9 +323,11 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
         u0 = u1; u1 = u2; v0 = v1; v1 = v2; w0 = w1; w1 = w2; t0 = t1; t1 = t2;
     };
 
-    for (int k = k0; k < k1; k += 2) {
+    for (int k = k0; k < k1; k += DEPTH) {
         plane(X, k);
         if (k + 1 < k1) plane(Y, k + 1);
+        if constexpr (DEPTH == 3)
+            if (k + 2 < k1) plane(Zs, k + 2);
     }
 
     if (NORM) {
