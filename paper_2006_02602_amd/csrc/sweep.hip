@@ -95,6 +95,9 @@ template hipError_t launch_sweep<float>(const Dims&, const Coef&, const SweepGeo
 // it.  Each cell is computed by exactly one launch with the same per-cell
 // code as the unsplit sweep, so the new state is bit-identical to it.
 
+// Tile shape of the exterior x slabs (2m <= 8 owned columns).
+constexpr int XS_TI = 16, XS_TJ = 32;
+
 // Cell x along `axis` lies within m of a cut between two subdomains.
 __device__ __forceinline__ bool near_cut(const SplitGeom& sg, int axis, int x)
 {
@@ -145,21 +148,26 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void interior_kernel(Dims d, Coef cd
     sweep_tile<Real, NORM>(d, c, tb, OwnInterior{sg}, q, epi, partials, L);
 }
 
-// Exterior work items, block b: first the x slabs (per cut: j tiles x k
-// chunks of kce planes), then the y slabs (per cut: i tiles x k chunks),
-// then the z slabs (per cut: i x j tiles, the 2m planes around the cut).
+// Exterior work items, block b: first the x slabs (per cut: 16 x 32 tiles,
+// j tiles x k chunks of kce planes), then the y slabs (per cut: i tiles x k
+// chunks), then the z slabs (per cut: i x j tiles, the 2m planes around the
+// cut).
 // Norm partials follow the interior launch's, at pidx = nblocks + b.
 template <typename Real, bool NORM, bool FIELD>
 __global__ __launch_bounds__(SW_TI * SW_TJ) void exterior_kernel(Dims d, Coef cd, SweepGeom g, SplitGeom sg,
                                                                  CStateT<Real> q, StateT<Real> qn,
                                                                  double* partials)
 {
-    __shared__ SweepLds<Real> L;
+    __shared__ union {
+        SweepLds<Real> yz;                       // 64 x 8 tiles for the y and z slabs
+        SweepLds<Real, XS_TI, XS_TJ> x;          // 16 x 32 tiles for the x slabs
+    } L;
     CoefR<Real> c = coef_as<Real>(cd);
     if constexpr (!FIELD) c.t_hot_field = nullptr;
     const int b = blockIdx.x;
     const int nkce = (d.nk + sg.kce - 1) / sg.kce;
-    const int per0 = g.tiles_j * nkce, per1 = g.tiles_i * nkce, per2 = g.tiles_i * g.tiles_j;
+    const int tjx = (d.nj + XS_TJ - 1) / XS_TJ;
+    const int per0 = tjx * nkce, per1 = g.tiles_i * nkce, per2 = g.tiles_i * g.tiles_j;
     const int n0 = (sg.P[0] - 1) * per0, n1 = (sg.P[1] - 1) * per1;
     TileBox tb;
     int axis, cut;
@@ -168,8 +176,8 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void exterior_kernel(Dims d, Coef cd
         const int r = b % per0;
         cut = (b / per0 + 1) * sg.e[0];
         tb.i0 = cut - sg.m;
-        tb.j0 = (r % g.tiles_j) * SW_TJ;
-        tb.k0 = (r / g.tiles_j) * sg.kce;
+        tb.j0 = (r % tjx) * XS_TJ;
+        tb.k0 = (r / tjx) * sg.kce;
         tb.k1 = min(tb.k0 + sg.kce, d.nk);
     } else if (b < n0 + n1) {
         axis = 1;
@@ -190,13 +198,17 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void exterior_kernel(Dims d, Coef cd
     }
     tb.pidx = g.nblocks + b;
     StepEpi<Real> epi{qn, Real(0)};
-    sweep_tile<Real, NORM>(d, c, tb, OwnSlab{sg, axis, cut}, q, epi, partials, L);
+    if (axis == 0)          // 2m <= 8 owned columns: a narrow tile wastes fewer lanes
+        sweep_tile<Real, NORM, OwnSlab, StepEpi<Real>, 3, XS_TI, XS_TJ>(d, c, tb, OwnSlab{sg, axis, cut}, q, epi,
+                                                                      partials, L.x);
+    else
+        sweep_tile<Real, NORM>(d, c, tb, OwnSlab{sg, axis, cut}, q, epi, partials, L.yz);
 }
 
 int exterior_blocks(const Dims& d, const SweepGeom& g, const SplitGeom& sg)
 {
     const int nkce = (d.nk + sg.kce - 1) / sg.kce;
-    return (sg.P[0] - 1) * g.tiles_j * nkce + (sg.P[1] - 1) * g.tiles_i * nkce +
+    return (sg.P[0] - 1) * ((d.nj + XS_TJ - 1) / XS_TJ) * nkce + (sg.P[1] - 1) * g.tiles_i * nkce +
            (sg.P[2] - 1) * g.tiles_i * g.tiles_j;
 }
 

@@ -18,18 +18,19 @@ namespace cav {
 // plane costs one barrier; global loads run two or three planes ahead.  Wall ghosts
 // are derived from interior cells (in LDS for the i/j walls, by recurrences
 // on the queues for the k walls); no ghost cell is read from HBM.
-// LDS of one sweep block: two planes of p (halo 2) and of u, v, w, T
-// (halo 1).
-template <typename Real>
+// LDS of one sweep block of TI x TJ threads: two planes of p (halo 2) and
+// of u, v, w, T (halo 1), and one norm slot per wavefront.
+template <typename Real, int TI_ = SW_TI, int TJ_ = SW_TJ>
 struct SweepLds {
-    static constexpr int TI = SW_TI, TJ = SW_TJ;
+    static constexpr int TI = TI_, TJ = TJ_;
     static constexpr int PW = TI + 4;              // row pitch, p
     static constexpr int UW = TI + 2;              // row pitch, u v w T
     static constexpr int PPL = (TJ + 4) * PW;      // plane, p
     static constexpr int UPL = (TJ + 2) * UW;      // plane, one of u v w T
+    static constexpr int NWAVE = TI * TJ / 64;
     Real p[2 * PPL];
     Real u[2 * 4 * UPL];
-    double red[TJ][NF];
+    double red[NWAVE][NF];
 };
 
 // What a sweep does with each cell's stars and residual: the pseudo-time
@@ -63,21 +64,22 @@ struct StepEpi {
     }
 };
 
-// Where one block works: columns [i0, i0+64) x [j0, j0+8), planes
+// Where one block works: columns [i0, i0+TI) x [j0, j0+TJ), planes
 // [k0, k1); its norm partial goes to slot pidx.
 struct TileBox {
     int i0, j0, k0, k1, pidx;
 };
 
-// Logical tile b of the regular tiling with k chunks of length kc.
+// Logical tile b of the regular TI x TJ tiling with k chunks of length kc.
+template <int TI = SW_TI, int TJ = SW_TJ>
 __device__ __forceinline__ TileBox tile_box(const Dims& d, int tiles_i, int tiles_j, int kc, int b)
 {
     const int bi = b % tiles_i;
     const int bj = (b / tiles_i) % tiles_j;
     const int bk = b / (tiles_i * tiles_j);
     TileBox t;
-    t.i0 = bi * SW_TI;
-    t.j0 = bj * SW_TJ;
+    t.i0 = bi * TI;
+    t.j0 = bj * TJ;
     t.k0 = bk * kc;
     t.k1 = min(t.k0 + kc, d.nk);
     t.pidx = b;
@@ -93,21 +95,29 @@ struct OwnAll {
 
 // One tile box: planes of its k range, cells for which own(i, j, k) holds
 // are updated (and enter the norm).  Used by the single-cavity sweep, the
-// batched kernel and the interior/exterior split.
-template <typename Real, bool NORM, typename Own, typename Epi, int DEPTH = 3>
+// batched kernel and the interior/exterior split.  The block has TI x TJ =
+// 512 threads: thread t = lane + TI * row works on column (i0 + lane,
+// j0 + row); TI >= 16 and TJ >= 8 (the halo roles below need 12 threads per
+// row and 8 rows).
+template <typename Real, bool NORM, typename Own, typename Epi, int DEPTH = 3, int TI = SW_TI, int TJ = SW_TJ>
 __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, const TileBox& tb, const Own& own,
-                                           const CStateT<Real>& q, Epi& epi, double* partials, SweepLds<Real>& L)
+                                           const CStateT<Real>& q, Epi& epi, double* partials,
+                                           SweepLds<Real, TI, TJ>& L)
 {
-    constexpr int TI = SW_TI, TJ = SW_TJ;
-    constexpr int PW = SweepLds<Real>::PW, UW = SweepLds<Real>::UW;
-    constexpr int PPL = SweepLds<Real>::PPL, UPL = SweepLds<Real>::UPL;
+    static_assert(TI * TJ == SW_TI * SW_TJ && TI >= 16 && TJ >= 8, "512-thread tiles, TI >= 16, TJ >= 8");
+    using Lds = SweepLds<Real, TI, TJ>;
+    constexpr int PW = Lds::PW, UW = Lds::UW;
+    constexpr int PPL = Lds::PPL, UPL = Lds::UPL;
     Real* const sP = L.p;
     Real* const sU = L.u;
 
     const int i0 = tb.i0, j0 = tb.j0;
     const int k0 = tb.k0, k1 = tb.k1;
 
-    const int lane = threadIdx.x, row = threadIdx.y;
+    // launched as SW_TI x SW_TJ threads; other shapes re-split the block
+    const int tid = threadIdx.x + SW_TI * threadIdx.y;
+    const int lane = TI == SW_TI ? (int)threadIdx.x : tid % TI;
+    const int row = TI == SW_TI ? (int)threadIdx.y : tid / TI;
     const int i = i0 + lane, j = j0 + row;
     // columns no owned cell's star reaches are neither loaded nor computed
     const bool active = i < d.ni && j < d.nj && own.column(i, j);
@@ -124,11 +134,12 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
     const int prow_lds = row < 2 ? row : TJ + row;
     const int prow_j = j0 - 2 + prow_lds;
     const bool ld_prow = has_prow && interior(i, prow_j) && own.column(i, prow_j);
-    // u v w T rows j0-1, j0+TJ: waves 0..7, field 1 + row/2
-    const int urow_f = FU + (row >> 1);
+    // u v w T rows j0-1, j0+TJ: rows 0..7, field 1 + row/2
+    const bool has_urow = row < 8;
+    const int urow_f = FU + (min(row, 7) >> 1);
     const int urow_lds = (row & 1) ? TJ + 1 : 0;
     const int urow_j = j0 - 1 + urow_lds;
-    const bool ld_urow = interior(i, urow_j) && own.column(i, urow_j);
+    const bool ld_urow = has_urow && interior(i, urow_j) && own.column(i, urow_j);
     // column halos of this wave's row: lanes 0..3 p (i0-2, i0-1, i0+TI,
     // i0+TI+1), lanes 4..11 u v w T (i0-1, i0+TI)
     const bool has_col = lane < 12;
@@ -234,7 +245,7 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
     sU[2 * UPL + lc_u] = w1;
     sU[3 * UPL + lc_u] = t1;
     if (has_prow) sP[prow_dst] = ld_prow ? Pg[off_prow + k0 * Z] : Real(0);
-    sU[urow_dst] = ld_urow ? URg[off_urow + k0 * Z] : Real(0);
+    if (has_urow) sU[urow_dst] = ld_urow ? URg[off_urow + k0 * Z] : Real(0);
     if (has_col) (col_f == FP ? sP : sU)[col_lds] = ld_col ? COLg[off_col + k0 * Z] : Real(0);
 
     // Loads run DEPTH planes ahead: what the iteration for plane k needs
@@ -287,7 +298,7 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
             nU[2 * UPL + lc_u] = w2;
             nU[3 * UPL + lc_u] = t2;
             if (has_prow) nP[prow_dst] = F.prow;
-            nU[urow_dst] = F.urow;
+            if (has_urow) nU[urow_dst] = F.urow;
             if (has_col) (col_f == FP ? nP : nU)[col_lds] = F.col;
         }
         if (k + DEPTH < k1) issue(F, k + DEPTH);
@@ -332,7 +343,7 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
 
     if (NORM) {
         // fixed-order block reduction: butterfly within the wavefront, then
-        // the 8 wavefront sums in order
+        // the wavefront sums in order
         auto& red = L.red;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -341,16 +352,17 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
             for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
             acc[f] = v;
         }
-        if (lane == 0) {
+        const int wl = tid & 63, wv = tid >> 6;
+        if (wl == 0) {
 #pragma unroll
-            for (int f = 0; f < NF; ++f) red[row][f] = acc[f];
+            for (int f = 0; f < NF; ++f) red[wv][f] = acc[f];
         }
         __syncthreads();
-        if (row == 0 && lane < NF) {
+        if (tid < NF) {
             double t = 0.0;
 #pragma unroll
-            for (int r = 0; r < TJ; ++r) t += red[r][lane];
-            partials[(size_t)tb.pidx * NF + lane] = t;
+            for (int r = 0; r < Lds::NWAVE; ++r) t += red[r][tid];
+            partials[(size_t)tb.pidx * NF + tid] = t;
         }
     }
 }
