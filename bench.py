@@ -136,13 +136,13 @@ def f32_leg(C, torch, steps):
 
 def batch_leg(C, torch, steps):
     """The batched form: 96 FP32 cubes of uneven edges and Rayleigh numbers,
-    k-chunk per edge and block count from the autotuner, `steps` steps
-    replayed from one HIP graph."""
+    tile shape and k chunk per edge and the block count from the autotuner,
+    `steps` steps replayed from one HIP graph."""
     from paper_2006_02602_amd import autotune
     from paper_2006_02602_amd.configs import batch_workload
     wl = batch_workload()
-    kcs = autotune.tune_kc([e for e, _, _ in wl], C.CAV_F32, cache_path="/tmp/cavity_autotune.json")
-    b = C.Batch([(C.Grid.cube(e, C.CAV_F32), C.Params(Ra=ra), kcs[e]) for e, ra, _ in wl])
+    shapes = autotune.tune_shapes([e for e, _, _ in wl], C.CAV_F32, cache_path="/tmp/cavity_autotune.json")
+    b = C.Batch([(C.Grid.cube(e, C.CAV_F32), C.Params(Ra=ra), shapes[e][1], shapes[e][0]) for e, ra, _ in wl])
     b.init([s for _, _, s in wl])
     nb, tb = autotune.tune_blocks(b)
     b.init([s for _, _, s in wl])
@@ -161,7 +161,9 @@ def batch_leg(C, torch, steps):
     return {"workload": "batch96_f32_edges24-96_ra1e3-1e6", "members": len(b), "cells": b.cells,
             "steps": steps, "value": b.cells * steps / dt, "unit": "grid-point updates/s",
             "ms_per_step": 1e3 * dt / steps, "launch": "one persistent kernel per step, %d steps in one HIP graph" % steps,
-            "autotuned_kc_per_edge": {str(k): v for k, v in kcs.items()}, "autotuned_blocks": nb,
+            "autotuned_tile_and_kc_per_edge": {str(k): {"tile": "%dx%d" % (v[0], 512 // v[0]), "kc": v[1]}
+                                               for k, v in shapes.items()},
+            "autotuned_blocks": nb,
             "block_timings_ms": {str(k): v for k, v in tb.items()},
             "bytes_per_step_algorithmic": 40 * b.cells,
             "GBs_algorithmic": 40 * b.cells / (dt / steps) / 1e9, "norms_finite": norms_ok}

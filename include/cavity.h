@@ -275,9 +275,9 @@ int cavity_adjoint_step(const cav_grid* grid, const cav_params* prm,
  * A batch advances n cavities of arbitrary sizes and parameters (all of one
  * dtype) together: every step is ONE launch of a persistent kernel whose
  * blocks walk a device work list of (cavity, tile column, k chunk) items,
- * each computed exactly as cavity_step computes that tile, so every
- * member's state is bit-identical to advancing it alone with the same
- * k-chunk length.  There is no halo exchange in the batched form. */
+ * each computed with the per-cell code of cavity_step, so every member's
+ * state is bit-identical to advancing it alone, whatever its tile shape and
+ * k-chunk length (only the grouping of the norm sums differs).  There is no halo exchange in the batched form. */
 typedef struct {
     cav_grid grid;          /* member grid; dtype must match the batch      */
     cav_params params;      /* member parameters                             */
@@ -286,6 +286,9 @@ typedef struct {
     void* ws;               /* device workspace                              */
     size_t ws_bytes;        /* >= cavity_workspace_bytes(grid)               */
     int32_t kc;             /* k planes per work item, 0 = whole columns    */
+    int32_t ti;             /* tile shape: 0 or 64 = 64 x 8 columns,
+                               32 = 32 x 16 (less lane waste on narrow
+                               cavities); the result does not depend on it  */
 } cav_batch_member;
 
 /* Host handle of a built batch (plain data; owns nothing). */

@@ -341,7 +341,8 @@ class Batch:
     """Many independent cavities advanced together (the batched form): one
     persistent launch per step over all members; optional graph replay.
 
-    members: list of (Grid, Params) or (Grid, Params, kc)."""
+    members: list of (Grid, Params), (Grid, Params, kc) or
+    (Grid, Params, kc, ti) with ti the tile width (0/64: 64 x 8, 32: 32 x 16)."""
 
     def __init__(self, members, device: str = "cuda"):
         import torch
@@ -351,6 +352,7 @@ class Batch:
         for m in members:
             g, p = m[0], m[1]
             kc = m[2] if len(m) > 2 else 0
+            ti = m[3] if len(m) > 3 else 0
             n = cavity_state_elems(g)
             if n == 0:
                 raise CavError(CAV_EINVAL, cavity_last_error())
@@ -364,7 +366,7 @@ class Batch:
             self.q.append(q)
             self.q_tmp.append(qt)
             self.ws.append(ws)
-            cm.append(CavBatchMember(g.c(), p.c(), q.data_ptr(), qt.data_ptr(), ws.data_ptr(), wb, kc))
+            cm.append(CavBatchMember(g.c(), p.c(), q.data_ptr(), qt.data_ptr(), ws.data_ptr(), wb, kc, ti))
         self._members = cm
         nb = cavity_batch_table_bytes(cm)
         if nb == 0:

@@ -54,7 +54,8 @@ class CavLayout(ctypes.Structure):
 
 class CavBatchMember(ctypes.Structure):
     _fields_ = [("grid", CavGrid), ("params", CavParams), ("q", ctypes.c_void_p), ("q_tmp", ctypes.c_void_p),
-                ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t), ("kc", ctypes.c_int32)]
+                ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t), ("kc", ctypes.c_int32),
+                ("ti", ctypes.c_int32)]
 
 
 class CavBatch(ctypes.Structure):

@@ -1,12 +1,13 @@
 """Autotuner of the batched form's launch shape.
 
-The tile is one 64 x 8 column block (one wavefront per j row); what the
-batched kernel leaves open is the number of k planes per work item (kc),
-per cavity size, and the number of persistent blocks.  For each distinct
-cube edge the tuner times a small batch of that edge over the candidate kc
-values with HIP events and keeps the fastest; then it times the whole batch
-over the candidate block counts.  Results can be cached in a JSON file keyed
-by device architecture, element type and edge.
+What the batched kernel leaves open, per cavity size, is the tile shape
+(64 x 8 columns, or 32 x 16 for narrow cavities, where a 64-wide tile would
+leave lanes idle) and the number of k planes per work item (kc), and, for
+the whole batch, the number of persistent blocks.  For each distinct cube
+edge the tuner times a small batch of that edge over every (tile, kc)
+candidate with HIP events and keeps the fastest; then it times the whole
+batch over the candidate block counts.  Results can be cached in a JSON file
+keyed by device architecture, element type and edge.
 """
 import json
 import os
@@ -16,6 +17,7 @@ import torch
 from . import Batch, Grid, Params
 
 KC_CANDIDATES = (4, 8, 16, 32, 0)        # 0 = whole columns (the cavity height per item)
+TI_CANDIDATES = (64, 32)                 # tile widths: 64 x 8 and 32 x 16 columns
 BLOCK_CANDIDATES = (256, 512, 768)
 
 
@@ -52,28 +54,31 @@ def _save(path, cache):
             json.dump(cache, f, indent=1, sort_keys=True)
 
 
-def tune_kc(edges, dtype, steps=4, reps=3, probe_members=6, cache_path=None):
-    """{edge: kc} for every distinct edge in `edges` (FP32 or FP64 cubes)."""
+def tune_shapes(edges, dtype, steps=4, reps=3, probe_members=6, cache_path=None):
+    """{edge: (ti, kc)} for every distinct edge in `edges` (FP32 or FP64
+    cubes): the tile width and k-chunk length that step a small batch of
+    that edge fastest."""
     cache = _load(cache_path)
     out = {}
     for e in sorted(set(edges)):
         key = "%s:dtype%d:edge%d" % (_arch(), dtype, e)
-        if key in cache:
-            out[e] = cache[key]["kc"]
+        if key in cache and "ti" in cache[key]:
+            out[e] = (cache[key]["ti"], cache[key]["kc"])
             continue
         g = Grid.cube(e, dtype)
-        best, timings = None, {}
-        for kc in KC_CANDIDATES:
-            if kc > e:
-                continue
-            b = Batch([(g, Params(Ra=1e4), kc)] * probe_members).init(range(probe_members))
-            ms = _time(lambda: b.step(steps), reps)
-            timings[str(kc)] = ms
-            if best is None or ms < timings[str(best)]:
-                best = kc
-            del b
+        best, best_ms, timings = None, None, {}
+        for ti in TI_CANDIDATES:
+            for kc in KC_CANDIDATES:
+                if kc > e:
+                    continue
+                b = Batch([(g, Params(Ra=1e4), kc, ti)] * probe_members).init(range(probe_members))
+                ms = _time(lambda: b.step(steps), reps)
+                timings["ti%d:kc%d" % (ti, kc)] = ms
+                if best_ms is None or ms < best_ms:
+                    best, best_ms = (ti, kc), ms
+                del b
         out[e] = best
-        cache[key] = {"kc": best, "ms_per_%d_steps" % steps: timings}
+        cache[key] = {"ti": best[0], "kc": best[1], "ms_per_%d_steps" % steps: timings}
     _save(cache_path, cache)
     return out
 

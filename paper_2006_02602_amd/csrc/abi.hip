@@ -224,19 +224,23 @@ int device_slots()
     return slots;
 }
 
-// Large enough for any k-chunk length (one partial per tile and plane).
+// Large enough for any k-chunk length and either tile shape (one partial
+// per tile and plane).
 size_t ws_bytes_of(const Dims& d)
 {
-    const size_t tiles = (size_t)((d.ni + SW_TI - 1) / SW_TI) * ((d.nj + SW_TJ - 1) / SW_TJ);
-    return WS_HEAD + tiles * d.nk * NF * sizeof(double);
+    const size_t wide = (size_t)((d.ni + SW_TI - 1) / SW_TI) * ((d.nj + SW_TJ - 1) / SW_TJ);
+    const size_t narrow = (size_t)((d.ni + NARROW_TI - 1) / NARROW_TI) * ((d.nj + NARROW_TJ - 1) / NARROW_TJ);
+    return WS_HEAD + std::max(wide, narrow) * d.nk * NF * sizeof(double);
 }
 
-// Work items of a batch member for k-chunk length kc (0 = whole columns).
-SweepGeom member_geom(const Dims& d, int kc)
+// Work items of a batch member for k-chunk length kc (0 = whole columns)
+// and tile width ti (SW_TI or NARROW_TI).
+SweepGeom member_geom(const Dims& d, int kc, int ti)
 {
     SweepGeom g;
-    g.tiles_i = (d.ni + SW_TI - 1) / SW_TI;
-    g.tiles_j = (d.nj + SW_TJ - 1) / SW_TJ;
+    const int tj = ti == NARROW_TI ? NARROW_TJ : SW_TJ;
+    g.tiles_i = (d.ni + ti - 1) / ti;
+    g.tiles_j = (d.nj + tj - 1) / tj;
     g.kc = (kc > 0 && kc < d.nk) ? kc : d.nk;
     g.nkc = (d.nk + g.kc - 1) / g.kc;
     g.nblocks = g.tiles_i * g.tiles_j * g.nkc;
@@ -252,12 +256,16 @@ int check_member(const cav_batch_member& m, int idx, int dtype)
     if (!m.q || !m.q_tmp || !m.ws) return fail(CAV_EINVAL, "batch member %d: q, q_tmp and ws must not be NULL", idx);
     if (m.q == m.q_tmp) return fail(CAV_EINVAL, "batch member %d: q and q_tmp must be distinct", idx);
     if (m.kc < 0) return fail(CAV_EINVAL, "batch member %d: kc = %d must be >= 0", idx, m.kc);
+    if (m.ti != 0 && m.ti != SW_TI && m.ti != NARROW_TI)
+        return fail(CAV_EINVAL, "batch member %d: ti = %d must be 0, %d or %d", idx, m.ti, SW_TI, NARROW_TI);
     const size_t need = ws_bytes_of(dims_of(&m.grid));
     if (m.ws_bytes < need) return fail(CAV_ESIZE, "batch member %d: ws_bytes %zu < required %zu", idx, m.ws_bytes, need);
     return CAV_OK;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int member_ti(const cav_batch_member& m) { return m.ti == NARROW_TI ? NARROW_TI : SW_TI; }
 
 template <typename Real>
 hipError_t batch_launches(const cav_batch& b, int32_t nsteps, int nblocks, int parity, hipStream_t stream, bool timed)
@@ -655,7 +663,8 @@ size_t cavity_batch_table_bytes(int32_t n, const cav_batch_member* members)
     size_t items = 0;
     for (int m = 0; m < n; ++m) {
         if (check_grid(&members[m].grid) != CAV_OK || members[m].kc < 0) return 0;
-        items += (size_t)member_geom(dims_of(&members[m].grid), members[m].kc).nblocks;
+        if (members[m].ti != 0 && members[m].ti != SW_TI && members[m].ti != NARROW_TI) return 0;
+        items += (size_t)member_geom(dims_of(&members[m].grid), members[m].kc, member_ti(members[m])).nblocks;
     }
     return align256(sizeof(BatchCav) * n) + sizeof(BatchItem) * items;
 }
@@ -678,9 +687,11 @@ int cavity_batch_build(int32_t n, const cav_batch_member* members, void* table, 
     for (int m = 0; m < n; ++m) {
         const cav_batch_member& mb = members[m];
         const Dims d = dims_of(&mb.grid);
-        const SweepGeom g = member_geom(d, mb.kc);
+        const int ti = member_ti(mb), tj = ti == NARROW_TI ? NARROW_TJ : SW_TJ;
+        const SweepGeom g = member_geom(d, mb.kc, ti);
         BatchCav& cv = cavs[m];
         cv.d = d;
+        cv.ti = ti;
         cv.tiles_i = g.tiles_i;
         cv.tiles_j = g.tiles_j;
         cv.kc = g.kc;
@@ -693,7 +704,7 @@ int cavity_batch_build(int32_t n, const cav_batch_member* members, void* table, 
         cells += (uint64_t)d.ni * d.nj * d.nk;
         for (int t = 0; t < g.nblocks; ++t) {
             const int bi = t % g.tiles_i, bj = (t / g.tiles_i) % g.tiles_j, bk = t / (g.tiles_i * g.tiles_j);
-            const long long ci = std::min(SW_TI, d.ni - bi * SW_TI), cj = std::min(SW_TJ, d.nj - bj * SW_TJ);
+            const long long ci = std::min(ti, d.ni - bi * ti), cj = std::min(tj, d.nj - bj * tj);
             const long long ck = std::min(g.kc, d.nk - bk * g.kc);
             work.push_back({{m, t}, ci * cj * ck});
         }

@@ -85,8 +85,12 @@ struct HaloGeom {
 };
 
 // One member of a batch and one work item (a tile column's k chunk).
+// Narrow tile of the batched form: 32 x 16 columns (same 512 threads).
+constexpr int NARROW_TI = 32, NARROW_TJ = 16;
+
 struct BatchCav {
     Dims d;
+    int ti;                               // tile width: SW_TI (64 x 8) or NARROW_TI (32 x 16)
     int tiles_i, tiles_j, kc, ntiles;     // ntiles = tiles_i * tiles_j * (k chunks)
     Coef c;
     void* q;                              // state, q_tmp the scratch state

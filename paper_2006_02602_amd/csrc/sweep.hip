@@ -252,7 +252,10 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void batch_kernel(const BatchCav* __
                                                               const BatchItem* __restrict__ items, int nitems,
                                                               int parity)
 {
-    __shared__ SweepLds<Real> L;
+    __shared__ union {
+        SweepLds<Real> wide;                             // 64 x 8 tiles
+        SweepLds<Real, NARROW_TI, NARROW_TJ> narrow;     // 32 x 16 tiles
+    } L;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const BatchItem w = items[it];
         const BatchCav& cv = cavs[w.cav];
@@ -267,9 +270,16 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void batch_kernel(const BatchCav* __
             qs.f[f] = cur + f * cv.fstride;
             qn.f[f] = nxt + f * cv.fstride;
         }
-        const TileBox tb = tile_box(d, cv.tiles_i, cv.tiles_j, cv.kc, w.tile);
         StepEpi<Real> epi{qn, Real(0)};
-        sweep_tile<Real, NORM, OwnAll, StepEpi<Real>, 2>(d, c, tb, OwnAll{}, qs, epi, cv.ws + WS_HEAD_DOUBLES, L);
+        if (cv.ti == NARROW_TI) {
+            const TileBox tb = tile_box<NARROW_TI, NARROW_TJ>(d, cv.tiles_i, cv.tiles_j, cv.kc, w.tile);
+            sweep_tile<Real, NORM, OwnAll, StepEpi<Real>, 2, NARROW_TI, NARROW_TJ>(
+                d, c, tb, OwnAll{}, qs, epi, cv.ws + WS_HEAD_DOUBLES, L.narrow);
+        } else {
+            const TileBox tb = tile_box(d, cv.tiles_i, cv.tiles_j, cv.kc, w.tile);
+            sweep_tile<Real, NORM, OwnAll, StepEpi<Real>, 2>(d, c, tb, OwnAll{}, qs, epi, cv.ws + WS_HEAD_DOUBLES,
+                                                             L.wide);
+        }
         __syncthreads();                  // LDS is reused by the next item
     }
 }

@@ -75,6 +75,22 @@ def test_batch_result_is_independent_of_k_chunks(C):
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
+def test_batch_result_is_independent_of_tile_shape(C, dtype):
+    """32 x 16 tiles give the same states as 64 x 8 tiles (and as the single
+    cavity), bit for bit; norms to rounding."""
+    say("batch tile shape", dtype)
+    a = C.Batch([(C.Grid(*n, dtype=dtype), C.Params(Ra=Ra), 0, 64) for n, Ra in MEMBERS]).init(range(len(MEMBERS)))
+    b = C.Batch([(C.Grid(*n, dtype=dtype), C.Params(Ra=Ra), kc, 32) for (n, Ra), kc in zip(MEMBERS, (0, 5, 8, 3, 16, 0))])
+    b.init(range(len(MEMBERS)))
+    a.step(5)
+    b.step(5)
+    for m, (n, _) in enumerate(MEMBERS):
+        g = C.Grid(*n, dtype=dtype)
+        assert np.array_equal(interior(C, g, a.state(m)), interior(C, g, b.state(m))), m
+        np.testing.assert_allclose(b.norms(m), a.norms(m), rtol=1e-12 if dtype == 0 else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
 def test_graph_replays_equal_eager_steps(C, dtype):
     import torch
     say("batch graph", dtype)
@@ -119,11 +135,11 @@ def test_batch_member_against_oracle(C):
 def test_autotuner_returns_valid_choices(C):
     from paper_2006_02602_amd import autotune
     say("autotune")
-    kcs = autotune.tune_kc([24, 32], dtype=1, steps=2, reps=1, probe_members=2)
-    assert set(kcs) == {24, 32}
-    for e, kc in kcs.items():
-        assert kc in autotune.KC_CANDIDATES and kc <= e
-    b = C.Batch([(C.Grid.cube(e, 1), C.Params(), kcs[e]) for e in (24, 32, 32)]).init([1, 2, 3])
+    shapes = autotune.tune_shapes([24, 32], dtype=1, steps=2, reps=1, probe_members=2)
+    assert set(shapes) == {24, 32}
+    for e, (ti, kc) in shapes.items():
+        assert ti in autotune.TI_CANDIDATES and kc in autotune.KC_CANDIDATES and kc <= e
+    b = C.Batch([(C.Grid.cube(e, 1), C.Params(), shapes[e][1], shapes[e][0]) for e in (24, 32, 32)]).init([1, 2, 3])
     nb, t = autotune.tune_blocks(b, steps=2, reps=1)
     assert nb in autotune.BLOCK_CANDIDATES and len(t) == len(autotune.BLOCK_CANDIDATES)
 
