@@ -209,6 +209,15 @@ def test_batch_validation():
     assert build([_member(wsb=8)]) == C.CAV_ESIZE                        # workspace too small
     assert build([_member(q=0x5000, qt=0x5000)]) == C.CAV_EINVAL         # q == q_tmp
     assert build([_member(kc=-1)]) == C.CAV_EINVAL
+    wide = _member((40, 8, 9))
+    wide.ti = 48                                                         # not a tile width
+    assert build([wide]) == C.CAV_EINVAL
+    assert C.cavity_batch_table_bytes([wide]) == 0
+    # a 40 x 8 plane is 1 wide tile but 2 narrow ones: the workspace covers both
+    narrow = _member((40, 8, 9))
+    narrow.ti = 32
+    assert C.cavity_batch_table_bytes([narrow]) > C.cavity_batch_table_bytes([_member((40, 8, 9))])
+    assert C.cavity_workspace_bytes(C.Grid(40, 8, 9)) == 64 + 2 * 9 * 5 * 8
     assert build(ok, tb=16) == C.CAV_ESIZE                               # table too small
     bad = _lib.CavBatch(None, 1, 1, 0, 0, 1)
     assert L.cavity_batch_step(ctypes.byref(bad), 1, 0, None) == C.CAV_EINVAL
