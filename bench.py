@@ -256,6 +256,21 @@ def adjoint_leg(C, torch):
     return out
 
 
+def small_case(C, torch):
+    """The 16^3 parity workload (Ra 1e3, 2x2x2 exchange, 100 steps): cache-
+    and launch-resident, so only the time per step is reported."""
+    from paper_2006_02602_amd.configs import C0
+    cav = C.Cavity(C0.grid, C0.params, C0.halo()).init(C0.seed, C0.noise)
+    cav.step(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cav.step(C0.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": "%s_split2x2x2" % C0.name, "steps": C0.steps, "us_per_step": 1e6 * dt / C0.steps,
+            "note": "3 launches per step (pack, unpack, sweep); launch-bound, no roofline claim"}
+
+
 def cpu_baseline(wl, budget_s):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     workload (same grid, parameters and halo; fewer steps)."""
@@ -365,6 +380,9 @@ def main():
     breakdown = {k: {"launches": n, "avg_us": round(1e3 * ms / n, 2)} for k, (n, ms) in sorted(kt.items())}
     log("bench: sweep %.1f us -> %.0f GB/s algorithmic" % (1e3 * sw_ms, achieved))
 
+    small = small_case(C, torch)
+    log("bench: small case", small)
+
     halo_res = None
     if not args.no_halo_bench:
         splits = wl.splits
@@ -426,6 +444,7 @@ def main():
         "ms_per_step_with_events": 1e3 * t_ev / K,
         "residual_norms": norms,
     }
+    line["small_case"] = small
     if halo_res is not None:
         line["halo"] = halo_res
     if f32 is not None:
