@@ -80,9 +80,10 @@ __device__ __forceinline__ double recip_pos(double x)
     return fma(y, e, y);
 }
 
-// FP32 forms: the hardware square root and a reciprocal estimate refined by
-// one Newton step.
-__device__ __forceinline__ float sqrt_pos(float x) { return __builtin_sqrtf(fmaxf(x, 1e-30f)); }
+// FP32 forms: the hardware square root (within 1 ulp; the argument is kept
+// above the denormal range) and a reciprocal estimate refined by one Newton
+// step.
+__device__ __forceinline__ float sqrt_pos(float x) { return __builtin_amdgcn_sqrtf(fmaxf(x, 1e-30f)); }
 
 __device__ __forceinline__ float recip_pos(float x)
 {
