@@ -224,13 +224,14 @@ int device_slots()
     return slots;
 }
 
-// Large enough for any k-chunk length and either tile shape (one partial
-// per tile and plane).
+// Large enough for any k-chunk length and any tile shape (one partial per
+// tile and plane).
 size_t ws_bytes_of(const Dims& d)
 {
     const size_t wide = (size_t)((d.ni + SW_TI - 1) / SW_TI) * ((d.nj + SW_TJ - 1) / SW_TJ);
     const size_t narrow = (size_t)((d.ni + NARROW_TI - 1) / NARROW_TI) * ((d.nj + NARROW_TJ - 1) / NARROW_TJ);
-    return WS_HEAD + std::max(wide, narrow) * d.nk * NF * sizeof(double);
+    const size_t f32 = (size_t)((d.ni + F32_TI - 1) / F32_TI) * ((d.nj + F32_TJ - 1) / F32_TJ);
+    return WS_HEAD + std::max(std::max(wide, narrow), f32) * d.nk * NF * sizeof(double);
 }
 
 // Work items of a batch member for k-chunk length kc (0 = whole columns)
@@ -316,7 +317,7 @@ int step_impl(const cav_grid* grid, const cav_params* prm, const cav_halo* halo,
     int rc;
     const Dims d = dims_of(grid);
     const Coef c = coef_of(grid, prm);
-    const SweepGeom g = sweep_geom(d, device_slots());
+    const SweepGeom g = step_geom<Real>(d, device_slots());
     double* wsd = static_cast<double*>(ws);
     double* partials = reinterpret_cast<double*>(static_cast<char*>(ws) + WS_HEAD);
     void* cur = q;

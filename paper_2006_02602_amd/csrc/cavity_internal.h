@@ -66,7 +66,17 @@ struct SweepGeom {
     int nkc;                  // k chunks
     int nblocks;              // tiles_i * tiles_j * nkc
 };
-SweepGeom sweep_geom(const Dims& d, int slots);     // slots: blocks resident at once
+// slots: blocks resident at once; ti x tj: the tile of the launch
+SweepGeom sweep_geom(const Dims& d, int slots, int ti = SW_TI, int tj = SW_TJ);
+// Tile of the single-cavity step sweep in FP32: 32 x 8 threads, four
+// wavefronts, so that three blocks stay resident per compute unit at that
+// kernel's register count (FP64 keeps SW_TI x SW_TJ, one block of eight).
+constexpr int F32_TI = 32, F32_TJ = 8;
+// Geometry of the step sweep for element type Real on `cus` compute units
+// (its tile, and the resident blocks per compute unit the occupancy query
+// reports).
+template <typename Real>
+SweepGeom step_geom(const Dims& d, int cus);
 
 struct Bcs {
     double t_hot, t_cold;

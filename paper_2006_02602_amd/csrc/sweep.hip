@@ -20,29 +20,41 @@
 
 namespace cav {
 
+// Tile of the step sweep: FP64 64 x 8 (eight wavefronts; at its register
+// count one block per compute unit), FP32 32 x 8 (four wavefronts; three
+// resident blocks per compute unit, whose barriers interleave).
+template <typename Real>
+struct StepTile {
+    static constexpr int TI = sizeof(Real) == 4 ? F32_TI : SW_TI;
+    static constexpr int TJ = sizeof(Real) == 4 ? F32_TJ : SW_TJ;
+    static constexpr int THREADS = TI * TJ;
+};
+
 // FIELD = false: the hot wall is the scalar t_hot, known at compile time to
 // need no field loads (the kernel the uniform-wall problem runs).
 template <typename Real, bool NORM, bool FIELD>
-__global__ __launch_bounds__(SW_TI * SW_TJ) void sweep_kernel(Dims d, Coef cd, SweepGeom g, CStateT<Real> q,
-                                                              StateT<Real> qn, double* partials)
+__global__ __launch_bounds__(StepTile<Real>::THREADS) void sweep_kernel(Dims d, Coef cd, SweepGeom g,
+                                                                        CStateT<Real> q, StateT<Real> qn,
+                                                                        double* partials)
 {
-    __shared__ SweepLds<Real> L;
+    constexpr int TI = StepTile<Real>::TI, TJ = StepTile<Real>::TJ;
+    __shared__ SweepLds<Real, TI, TJ> L;
     CoefR<Real> c = coef_as<Real>(cd);
     if constexpr (!FIELD) c.t_hot_field = nullptr;
-    const TileBox tb = tile_box(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
+    const TileBox tb = tile_box<TI, TJ>(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
     StepEpi<Real> epi{qn, Real(0)};
-    sweep_tile<Real, NORM>(d, c, tb, OwnAll{}, q, epi, partials, L);
+    sweep_tile<Real, NORM, OwnAll, StepEpi<Real>, 3, TI, TJ>(d, c, tb, OwnAll{}, q, epi, partials, L);
 }
 
-SweepGeom sweep_geom(const Dims& d, int slots)
+SweepGeom sweep_geom(const Dims& d, int slots, int ti, int tj)
 {
     SweepGeom g;
-    g.tiles_i = (d.ni + SW_TI - 1) / SW_TI;
-    g.tiles_j = (d.nj + SW_TJ - 1) / SW_TJ;
+    g.tiles_i = (d.ni + ti - 1) / ti;
+    g.tiles_j = (d.nj + tj - 1) / tj;
     const int tiles = g.tiles_i * g.tiles_j;
     // Split the k columns into nkc chunks so that the launch finishes
-    // earliest: blocks run in rounds of `slots` (one resident block per
-    // compute unit), a block costs its planes plus ~3 planes of start-up
+    // earliest: blocks run in rounds of `slots` (the blocks resident at
+    // once), a block costs its planes plus ~3 planes of start-up
     // (the queue and halo planes it loads before its first plane).
     const int overhead = 3;
     long long best_cost = -1;
@@ -65,10 +77,30 @@ SweepGeom sweep_geom(const Dims& d, int slots)
 }
 
 template <typename Real>
+SweepGeom step_geom(const Dims& d, int cus)
+{
+    // resident blocks per compute unit of the step kernel (registers and LDS
+    // decide it); the same for every launch on this device
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_kernel<Real, false, false>,
+                                                         StepTile<Real>::THREADS, 0) != hipSuccess ||
+            n < 1)
+            n = 1;
+        per_cu = n;
+    }
+    return sweep_geom(d, cus * per_cu, StepTile<Real>::TI, StepTile<Real>::TJ);
+}
+template SweepGeom step_geom<double>(const Dims&, int);
+template SweepGeom step_geom<float>(const Dims&, int);
+
+// g comes from step_geom<Real>.
+template <typename Real>
 hipError_t launch_sweep(const Dims& d, const Coef& c, const SweepGeom& g, CStateT<Real> q, StateT<Real> qn,
                         double* partials, bool with_norm, hipStream_t s)
 {
-    dim3 block(SW_TI, SW_TJ), grid(g.nblocks);
+    dim3 block(SW_TI, StepTile<Real>::THREADS / SW_TI), grid(g.nblocks);
     if (c.t_hot_field) {
         if (with_norm)
             sweep_kernel<Real, true, true><<<grid, block, 0, s>>>(d, c, g, q, qn, partials);

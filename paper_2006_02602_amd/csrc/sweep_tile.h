@@ -96,15 +96,15 @@ struct OwnAll {
 // One tile box: planes of its k range, cells for which own(i, j, k) holds
 // are updated (and enter the norm).  Used by the single-cavity sweep, the
 // batched kernel and the interior/exterior split.  The block has TI x TJ =
-// 512 threads: thread t = lane + TI * row works on column (i0 + lane,
-// j0 + row); TI >= 16 and TJ >= 8 (the halo roles below need 12 threads per
-// row and 8 rows).
+// 512 or 256 threads, launched as SW_TI x (TI TJ / SW_TI): thread t = lane +
+// TI * row works on column (i0 + lane, j0 + row); TI >= 16 and TJ >= 8 (the
+// halo roles below need 12 threads per row and 8 rows).
 template <typename Real, bool NORM, typename Own, typename Epi, int DEPTH = 3, int TI = SW_TI, int TJ = SW_TJ>
 __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, const TileBox& tb, const Own& own,
                                            const CStateT<Real>& q, Epi& epi, double* partials,
                                            SweepLds<Real, TI, TJ>& L)
 {
-    static_assert(TI * TJ == SW_TI * SW_TJ && TI >= 16 && TJ >= 8, "512-thread tiles, TI >= 16, TJ >= 8");
+    static_assert((TI * TJ == 512 || TI * TJ == 256) && TI >= 16 && TJ >= 8, "512- or 256-thread tiles, TI >= 16, TJ >= 8");
     using Lds = SweepLds<Real, TI, TJ>;
     constexpr int PW = Lds::PW, UW = Lds::UW;
     constexpr int PPL = Lds::PPL, UPL = Lds::UPL;
@@ -114,7 +114,7 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
     const int i0 = tb.i0, j0 = tb.j0;
     const int k0 = tb.k0, k1 = tb.k1;
 
-    // launched as SW_TI x SW_TJ threads; other shapes re-split the block
+    // launched as SW_TI x (TI TJ / SW_TI) threads; other shapes re-split the block
     const int tid = threadIdx.x + SW_TI * threadIdx.y;
     const int lane = TI == SW_TI ? (int)threadIdx.x : tid % TI;
     const int row = TI == SW_TI ? (int)threadIdx.y : tid / TI;

@@ -218,6 +218,8 @@ def test_batch_validation():
     narrow.ti = 32
     assert C.cavity_batch_table_bytes([narrow]) > C.cavity_batch_table_bytes([_member((40, 8, 9))])
     assert C.cavity_workspace_bytes(C.Grid(40, 8, 9)) == 64 + 2 * 9 * 5 * 8
+    # 40 x 24: 3 wide (64 x 8), 4 narrow (32 x 16) and 6 FP32 step (32 x 8) tiles
+    assert C.cavity_workspace_bytes(C.Grid(40, 24, 9)) == 64 + 6 * 9 * 5 * 8
     assert build(ok, tb=16) == C.CAV_ESIZE                               # table too small
     bad = _lib.CavBatch(None, 1, 1, 0, 0, 1)
     assert L.cavity_batch_step(ctypes.byref(bad), 1, 0, None) == C.CAV_EINVAL
