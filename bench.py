@@ -161,7 +161,7 @@ def batch_leg(C, torch, steps):
     return {"workload": "batch96_f32_edges24-96_ra1e3-1e6", "members": len(b), "cells": b.cells,
             "steps": steps, "value": b.cells * steps / dt, "unit": "grid-point updates/s",
             "ms_per_step": 1e3 * dt / steps, "launch": "one persistent kernel per step, %d steps in one HIP graph" % steps,
-            "autotuned_tile_and_kc_per_edge": {str(k): {"tile": "%dx%d" % (v[0], 512 // v[0]), "kc": v[1]}
+            "autotuned_tile_and_kc_per_edge": {str(k): {"tile": "%dx%d" % C.batch_tile(C.CAV_F32, v[0]), "kc": v[1]}
                                                for k, v in shapes.items()},
             "autotuned_blocks": nb,
             "block_timings_ms": {str(k): v for k, v in tb.items()},

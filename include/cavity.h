@@ -286,9 +286,13 @@ typedef struct {
     void* ws;               /* device workspace                              */
     size_t ws_bytes;        /* >= cavity_workspace_bytes(grid)               */
     int32_t kc;             /* k planes per work item, 0 = whole columns    */
-    int32_t ti;             /* tile shape: 0 or 64 = 64 x 8 columns,
-                               32 = 32 x 16 (less lane waste on narrow
-                               cavities); the result does not depend on it  */
+    int32_t ti;             /* tile width: 0 = the wide shape; CAV_F64:
+                               64 = 64 x 8 or 32 = 32 x 16 columns (512
+                               threads); CAV_F32: 32 = 32 x 8 or 16 = 16 x
+                               16 (256 threads).  The narrow shape wastes
+                               fewer lanes on narrow cavities; the result
+                               does not depend on it; other values are
+                               CAV_EINVAL                                   */
 } cav_batch_member;
 
 /* Host handle of a built batch (plain data; owns nothing). */

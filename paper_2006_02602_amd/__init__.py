@@ -143,6 +143,19 @@ def cavity_state_elems(grid) -> int:
     return int(lib().cavity_state_elems(ctypes.byref(_grid(grid))))
 
 
+# Tile widths of the batched kernel per element type, (wide, narrow); the
+# tile has 512 (FP64) or 256 (FP32) threads, so its height follows.
+BATCH_TILE_WIDTHS = {CAV_F64: (64, 32), CAV_F32: (32, 16)}
+
+
+def batch_tile(dtype: int, ti: int = 0):
+    """(columns along i, rows along j) of the batched tile of width ti (0 =
+    the wide shape) for element type dtype."""
+    wide, narrow = BATCH_TILE_WIDTHS[dtype]
+    w = narrow if ti == narrow else wide
+    return w, (256 if dtype == CAV_F32 else 512) // w
+
+
 def cavity_workspace_bytes(grid) -> int:
     return int(lib().cavity_workspace_bytes(ctypes.byref(_grid(grid))))
 
@@ -342,7 +355,8 @@ class Batch:
     persistent launch per step over all members; optional graph replay.
 
     members: list of (Grid, Params), (Grid, Params, kc) or
-    (Grid, Params, kc, ti) with ti the tile width (0/64: 64 x 8, 32: 32 x 16)."""
+    (Grid, Params, kc, ti) with ti the tile width: 0 = the wide shape; FP64
+    64 (64 x 8) or 32 (32 x 16); FP32 32 (32 x 8) or 16 (16 x 16)."""
 
     def __init__(self, members, device: str = "cuda"):
         import torch

@@ -1,8 +1,9 @@
 """Autotuner of the batched form's launch shape.
 
 What the batched kernel leaves open, per cavity size, is the tile shape
-(64 x 8 columns, or 32 x 16 for narrow cavities, where a 64-wide tile would
-leave lanes idle) and the number of k planes per work item (kc), and, for
+(the element type's wide tile, or its narrow one for narrow cavities, where
+a wide tile would leave lanes idle: FP64 64 x 8 or 32 x 16, FP32 32 x 8 or
+16 x 16) and the number of k planes per work item (kc), and, for
 the whole batch, the number of persistent blocks.  For each distinct cube
 edge the tuner times a small batch of that edge over every (tile, kc)
 candidate with HIP events and keeps the fastest; then it times the whole
@@ -14,11 +15,16 @@ import os
 
 import torch
 
-from . import Batch, Grid, Params
+from . import BATCH_TILE_WIDTHS, Batch, Grid, Params
 
 KC_CANDIDATES = (4, 8, 16, 32, 0)        # 0 = whole columns (the cavity height per item)
-TI_CANDIDATES = (64, 32)                 # tile widths: 64 x 8 and 32 x 16 columns
-BLOCK_CANDIDATES = (256, 512, 768)
+BLOCK_CANDIDATES = (256, 512, 768, 1024)
+CACHE_VERSION = 2                        # bump when the tile shapes change
+
+
+def ti_candidates(dtype):
+    """Tile widths the tuner tries for element type dtype (wide, narrow)."""
+    return BATCH_TILE_WIDTHS[dtype]
 
 
 def _arch():
@@ -61,13 +67,13 @@ def tune_shapes(edges, dtype, steps=4, reps=3, probe_members=6, cache_path=None)
     cache = _load(cache_path)
     out = {}
     for e in sorted(set(edges)):
-        key = "%s:dtype%d:edge%d" % (_arch(), dtype, e)
+        key = "v%d:%s:dtype%d:edge%d" % (CACHE_VERSION, _arch(), dtype, e)
         if key in cache and "ti" in cache[key]:
             out[e] = (cache[key]["ti"], cache[key]["kc"])
             continue
         g = Grid.cube(e, dtype)
         best, best_ms, timings = None, None, {}
-        for ti in TI_CANDIDATES:
+        for ti in ti_candidates(dtype):
             for kc in KC_CANDIDATES:
                 if kc > e:
                     continue

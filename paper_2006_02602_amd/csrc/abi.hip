@@ -224,28 +224,36 @@ int device_slots()
     return slots;
 }
 
-// Large enough for any k-chunk length and any tile shape (one partial per
-// tile and plane).
-size_t ws_bytes_of(const Dims& d)
+// Large enough for any k-chunk length and any tile shape the type's
+// kernels use (one partial per tile and plane).
+size_t ws_bytes_of(const Dims& d, bool f32)
 {
-    const size_t wide = (size_t)((d.ni + SW_TI - 1) / SW_TI) * ((d.nj + SW_TJ - 1) / SW_TJ);
-    const size_t narrow = (size_t)((d.ni + NARROW_TI - 1) / NARROW_TI) * ((d.nj + NARROW_TJ - 1) / NARROW_TJ);
-    const size_t f32 = (size_t)((d.ni + F32_TI - 1) / F32_TI) * ((d.nj + F32_TJ - 1) / F32_TJ);
-    return WS_HEAD + std::max(std::max(wide, narrow), f32) * d.nk * NF * sizeof(double);
+    auto tiles = [&](int ti, int tj) { return (size_t)((d.ni + ti - 1) / ti) * ((d.nj + tj - 1) / tj); };
+    size_t t = std::max(tiles(SW_TI, SW_TJ), tiles(batch_wide_ti(f32), batch_tj(f32, batch_wide_ti(f32))));
+    t = std::max(t, tiles(batch_narrow_ti(f32), batch_tj(f32, batch_narrow_ti(f32))));
+    if (f32) t = std::max(t, tiles(F32_TI, F32_TJ));
+    return WS_HEAD + t * d.nk * NF * sizeof(double);
 }
+size_t ws_bytes_of(const cav_grid* g) { return ws_bytes_of(dims_of(g), g->dtype == CAV_F32); }
 
 // Work items of a batch member for k-chunk length kc (0 = whole columns)
-// and tile width ti (SW_TI or NARROW_TI).
-SweepGeom member_geom(const Dims& d, int kc, int ti)
+// and tile width ti (batch_wide_ti or batch_narrow_ti of the type).
+SweepGeom member_geom(const Dims& d, int kc, int ti, bool f32)
 {
     SweepGeom g;
-    const int tj = ti == NARROW_TI ? NARROW_TJ : SW_TJ;
+    const int tj = batch_tj(f32, ti);
     g.tiles_i = (d.ni + ti - 1) / ti;
     g.tiles_j = (d.nj + tj - 1) / tj;
     g.kc = (kc > 0 && kc < d.nk) ? kc : d.nk;
     g.nkc = (d.nk + g.kc - 1) / g.kc;
     g.nblocks = g.tiles_i * g.tiles_j * g.nkc;
     return g;
+}
+
+bool ti_valid(const cav_batch_member& m)
+{
+    const bool f32 = m.grid.dtype == CAV_F32;
+    return m.ti == 0 || m.ti == batch_wide_ti(f32) || m.ti == batch_narrow_ti(f32);
 }
 
 int check_member(const cav_batch_member& m, int idx, int dtype)
@@ -257,16 +265,22 @@ int check_member(const cav_batch_member& m, int idx, int dtype)
     if (!m.q || !m.q_tmp || !m.ws) return fail(CAV_EINVAL, "batch member %d: q, q_tmp and ws must not be NULL", idx);
     if (m.q == m.q_tmp) return fail(CAV_EINVAL, "batch member %d: q and q_tmp must be distinct", idx);
     if (m.kc < 0) return fail(CAV_EINVAL, "batch member %d: kc = %d must be >= 0", idx, m.kc);
-    if (m.ti != 0 && m.ti != SW_TI && m.ti != NARROW_TI)
-        return fail(CAV_EINVAL, "batch member %d: ti = %d must be 0, %d or %d", idx, m.ti, SW_TI, NARROW_TI);
-    const size_t need = ws_bytes_of(dims_of(&m.grid));
+    const bool f32 = dtype == CAV_F32;
+    if (!ti_valid(m))
+        return fail(CAV_EINVAL, "batch member %d: ti = %d must be 0, %d or %d", idx, m.ti, batch_wide_ti(f32),
+                    batch_narrow_ti(f32));
+    const size_t need = ws_bytes_of(&m.grid);
     if (m.ws_bytes < need) return fail(CAV_ESIZE, "batch member %d: ws_bytes %zu < required %zu", idx, m.ws_bytes, need);
     return CAV_OK;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int member_ti(const cav_batch_member& m) { return m.ti == NARROW_TI ? NARROW_TI : SW_TI; }
+int member_ti(const cav_batch_member& m)
+{
+    const bool f32 = m.grid.dtype == CAV_F32;
+    return m.ti == batch_narrow_ti(f32) ? batch_narrow_ti(f32) : batch_wide_ti(f32);
+}
 
 template <typename Real>
 hipError_t batch_launches(const cav_batch& b, int32_t nsteps, int nblocks, int parity, hipStream_t stream, bool timed)
@@ -467,7 +481,7 @@ int cavity_layout(const cav_grid* grid, cav_layout* out)
 size_t cavity_workspace_bytes(const cav_grid* grid)
 {
     if (check_grid(grid) != CAV_OK) return 0;
-    return ws_bytes_of(dims_of(grid));
+    return ws_bytes_of(grid);
 }
 
 size_t halo_buffer_bytes(const cav_grid* grid, const cav_halo* halo)
@@ -510,7 +524,7 @@ int cavity_step(const cav_grid* grid, const cav_params* prm, const cav_halo* hal
     if (!q || !q_tmp || !ws) return fail(CAV_EINVAL, "q, q_tmp and ws must not be NULL");
     if (q == q_tmp) return fail(CAV_EINVAL, "q and q_tmp must be distinct buffers");
     const Dims d = dims_of(grid);
-    const size_t need_ws = ws_bytes_of(d);
+    const size_t need_ws = ws_bytes_of(grid);
     if (ws_bytes < need_ws) return fail(CAV_ESIZE, "ws_bytes %zu < required %zu", ws_bytes, need_ws);
     HaloGeom hg;
     if (halo) {
@@ -535,7 +549,7 @@ int cavity_step_overlap(const cav_grid* grid, const cav_params* prm, const cav_h
     if (!q || !q_tmp || !ws) return fail(CAV_EINVAL, "q, q_tmp and ws must not be NULL");
     if (q == q_tmp) return fail(CAV_EINVAL, "q and q_tmp must be distinct buffers");
     const Dims d = dims_of(grid);
-    const size_t need_ws = ws_bytes_of(d);
+    const size_t need_ws = ws_bytes_of(grid);
     if (ws_bytes < need_ws) return fail(CAV_ESIZE, "ws_bytes %zu < required %zu", ws_bytes, need_ws);
     HaloGeom hg;
     if ((rc = check_halo(grid, halo, &hg))) return rc;
@@ -577,7 +591,7 @@ int cavity_residual_norm(const cav_grid* grid, const void* ws, size_t ws_bytes, 
     int rc;
     if ((rc = check_grid(grid))) return rc;
     if (!ws || !out5) return fail(CAV_EINVAL, "ws and out5 must not be NULL");
-    const size_t need = ws_bytes_of(dims_of(grid));
+    const size_t need = ws_bytes_of(grid);
     if (ws_bytes < need) return fail(CAV_ESIZE, "ws_bytes %zu < required %zu", ws_bytes, need);
     hipError_t e = hipMemcpyAsync(out5, ws, NF * sizeof(double), hipMemcpyDeviceToHost, stream);
     if (e != hipSuccess) return hip_fail("norm copy", e);
@@ -596,7 +610,7 @@ int cavity_nusselt(const cav_grid* grid, const cav_params* prm, const void* q, v
     if (!q || !ws || !out) return fail(CAV_EINVAL, "q, ws and out must not be NULL");
     if (prm->t_hot == prm->t_cold) return fail(CAV_EINVAL, "t_hot == t_cold: the Nusselt number is undefined");
     const Dims d = dims_of(grid);
-    const size_t need = ws_bytes_of(d);
+    const size_t need = ws_bytes_of(grid);
     if (ws_bytes < need) return fail(CAV_ESIZE, "ws_bytes %zu < required %zu", ws_bytes, need);
     double* slot = static_cast<double*>(ws) + 6;
     const Bcs bc{prm->t_hot, prm->t_cold, static_cast<const double*>(prm->t_hot_field)};
@@ -664,8 +678,9 @@ size_t cavity_batch_table_bytes(int32_t n, const cav_batch_member* members)
     size_t items = 0;
     for (int m = 0; m < n; ++m) {
         if (check_grid(&members[m].grid) != CAV_OK || members[m].kc < 0) return 0;
-        if (members[m].ti != 0 && members[m].ti != SW_TI && members[m].ti != NARROW_TI) return 0;
-        items += (size_t)member_geom(dims_of(&members[m].grid), members[m].kc, member_ti(members[m])).nblocks;
+        if (!ti_valid(members[m])) return 0;
+        items += (size_t)member_geom(dims_of(&members[m].grid), members[m].kc, member_ti(members[m]),
+                                     members[m].grid.dtype == CAV_F32).nblocks;
     }
     return align256(sizeof(BatchCav) * n) + sizeof(BatchItem) * items;
 }
@@ -688,8 +703,9 @@ int cavity_batch_build(int32_t n, const cav_batch_member* members, void* table, 
     for (int m = 0; m < n; ++m) {
         const cav_batch_member& mb = members[m];
         const Dims d = dims_of(&mb.grid);
-        const int ti = member_ti(mb), tj = ti == NARROW_TI ? NARROW_TJ : SW_TJ;
-        const SweepGeom g = member_geom(d, mb.kc, ti);
+        const bool f32 = dtype == CAV_F32;
+        const int ti = member_ti(mb), tj = batch_tj(f32, ti);
+        const SweepGeom g = member_geom(d, mb.kc, ti, f32);
         BatchCav& cv = cavs[m];
         cv.d = d;
         cv.ti = ti;

@@ -257,11 +257,19 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
 {
     const CoefR<double> c = coef_as<double>(cd);
     const long long n = (long long)d.ni * d.nj * d.nk;
-    const long long idx = (long long)blockIdx.x * ADJ_THREADS + threadIdx.x;
-    if (idx >= n) return;
-    const int i = (int)(idx % d.ni);
-    const long long r = idx / d.ni;
-    const int j = (int)(r % d.nj), k = (int)(r / d.nj);
+    // Blocks go to the 8 XCDs round-robin; XCD x walks the rows j of its
+    // slab [j0, j0 + w) plane after plane, so that the records a cell reads
+    // from its y neighbours (adjacent rows) and z neighbours (the same rows
+    // one plane away, w rows earlier) are in that XCD's L2.
+    const int x = blockIdx.x & 7;
+    const int j0 = (int)((long long)x * d.nj / 8);
+    const int w = (int)((long long)(x + 1) * d.nj / 8) - j0;
+    const long long cl = (long long)(blockIdx.x >> 3) * ADJ_THREADS + threadIdx.x;
+    if (cl >= (long long)d.ni * w * d.nk) return;
+    const int i = (int)(cl % d.ni);
+    const long long r = cl / d.ni;
+    const int j = j0 + (int)(r % w), k = (int)(r / w);
+    const long long idx = i + (long long)d.ni * (j + (long long)d.nj * k);
     const int o = cell_off(d, i, j, k);
     auto R = [&](int v, long long m) { return rec[(size_t)v * n + m]; };
     const double ctr = -2.0 * ((c.ix2 + c.iy2) + c.iz2);
@@ -437,8 +445,11 @@ hipError_t launch_adjoint_step(const Dims& d, const Coef& c, const SweepGeom& g,
         sum_kernel<<<1, ADJ_THREADS, 0, s>>>(part, g.nblocks, NF, dra, 1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    adjoint_gather_kernel<<<(unsigned)((n + ADJ_THREADS - 1) / ADJ_THREADS), ADJ_THREADS, 0, s>>>(
-        d, c, q, lam_in, psum, rec, lam_out, dthot);
+    // 8 j slabs (one per XCD), as many blocks for each as the widest needs
+    const long long wmax = (d.nj + 7) / 8;
+    const long long per_xcd = ((long long)d.ni * wmax * d.nk + ADJ_THREADS - 1) / ADJ_THREADS;
+    adjoint_gather_kernel<<<(unsigned)(8 * per_xcd), ADJ_THREADS, 0, s>>>(d, c, q, lam_in, psum, rec, lam_out,
+                                                                         dthot);
     return hipGetLastError();
 }
 

@@ -94,13 +94,20 @@ struct HaloGeom {
     int face_blocks;          // blocks per (subdomain, face)
 };
 
-// One member of a batch and one work item (a tile column's k chunk).
-// Narrow tile of the batched form: 32 x 16 columns (same 512 threads).
-constexpr int NARROW_TI = 32, NARROW_TJ = 16;
+// Tile shapes of the batched kernel, a wide and a narrow one per element
+// type, both of the type's block size: FP64 64 x 8 and 32 x 16 (512
+// threads); FP32 32 x 8 and 16 x 16 (256 threads, so that two blocks stay
+// resident per compute unit).  The narrow shape wastes fewer lanes on
+// narrow cavities.
+constexpr int batch_threads(bool f32) { return f32 ? 256 : 512; }
+constexpr int batch_wide_ti(bool f32) { return f32 ? 32 : 64; }
+constexpr int batch_narrow_ti(bool f32) { return f32 ? 16 : 32; }
+constexpr int batch_tj(bool f32, int ti) { return batch_threads(f32) / ti; }
 
+// One member of a batch and one work item (a tile column's k chunk).
 struct BatchCav {
     Dims d;
-    int ti;                               // tile width: SW_TI (64 x 8) or NARROW_TI (32 x 16)
+    int ti;                               // tile width: batch_wide_ti or batch_narrow_ti of the type
     int tiles_i, tiles_j, kc, ntiles;     // ntiles = tiles_i * tiles_j * (k chunks)
     Coef c;
     void* q;                              // state, q_tmp the scratch state

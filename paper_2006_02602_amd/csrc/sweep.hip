@@ -279,14 +279,25 @@ template hipError_t launch_split<float>(const Dims&, const Coef&, const SweepGeo
 // item is one tile column's k chunk of one member, computed by the same
 // sweep_tile as the single-cavity sweep.  `parity` selects which of q and
 // q_tmp holds the current state of every member.
+template <typename Real>
+struct BatchTiles {
+    static constexpr bool F32 = sizeof(Real) == 4;
+    static constexpr int THREADS = batch_threads(F32);
+    static constexpr int WTI = batch_wide_ti(F32), WTJ = batch_tj(F32, WTI);
+    static constexpr int NTI = batch_narrow_ti(F32), NTJ = batch_tj(F32, NTI);
+    // prefetch depth: the FP64 kernel would spill a third register set
+    static constexpr int DEPTH = F32 ? 3 : 2;
+};
+
 template <typename Real, bool NORM>
-__global__ __launch_bounds__(SW_TI * SW_TJ) void batch_kernel(const BatchCav* __restrict__ cavs,
-                                                              const BatchItem* __restrict__ items, int nitems,
-                                                              int parity)
+__global__ __launch_bounds__(BatchTiles<Real>::THREADS) void batch_kernel(const BatchCav* __restrict__ cavs,
+                                                                          const BatchItem* __restrict__ items,
+                                                                          int nitems, int parity)
 {
+    using BT = BatchTiles<Real>;
     __shared__ union {
-        SweepLds<Real> wide;                             // 64 x 8 tiles
-        SweepLds<Real, NARROW_TI, NARROW_TJ> narrow;     // 32 x 16 tiles
+        SweepLds<Real, BT::WTI, BT::WTJ> wide;
+        SweepLds<Real, BT::NTI, BT::NTJ> narrow;
     } L;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const BatchItem w = items[it];
@@ -303,14 +314,14 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void batch_kernel(const BatchCav* __
             qn.f[f] = nxt + f * cv.fstride;
         }
         StepEpi<Real> epi{qn, Real(0)};
-        if (cv.ti == NARROW_TI) {
-            const TileBox tb = tile_box<NARROW_TI, NARROW_TJ>(d, cv.tiles_i, cv.tiles_j, cv.kc, w.tile);
-            sweep_tile<Real, NORM, OwnAll, StepEpi<Real>, 2, NARROW_TI, NARROW_TJ>(
+        if (cv.ti == BT::NTI) {
+            const TileBox tb = tile_box<BT::NTI, BT::NTJ>(d, cv.tiles_i, cv.tiles_j, cv.kc, w.tile);
+            sweep_tile<Real, NORM, OwnAll, StepEpi<Real>, BT::DEPTH, BT::NTI, BT::NTJ>(
                 d, c, tb, OwnAll{}, qs, epi, cv.ws + WS_HEAD_DOUBLES, L.narrow);
         } else {
-            const TileBox tb = tile_box(d, cv.tiles_i, cv.tiles_j, cv.kc, w.tile);
-            sweep_tile<Real, NORM, OwnAll, StepEpi<Real>, 2>(d, c, tb, OwnAll{}, qs, epi, cv.ws + WS_HEAD_DOUBLES,
-                                                             L.wide);
+            const TileBox tb = tile_box<BT::WTI, BT::WTJ>(d, cv.tiles_i, cv.tiles_j, cv.kc, w.tile);
+            sweep_tile<Real, NORM, OwnAll, StepEpi<Real>, BT::DEPTH, BT::WTI, BT::WTJ>(
+                d, c, tb, OwnAll{}, qs, epi, cv.ws + WS_HEAD_DOUBLES, L.wide);
         }
         __syncthreads();                  // LDS is reused by the next item
     }
@@ -320,7 +331,7 @@ template <typename Real>
 hipError_t launch_batch(const BatchCav* cavs, const BatchItem* items, int nitems, int parity, bool with_norm,
                         int nblocks, hipStream_t s)
 {
-    dim3 block(SW_TI, SW_TJ), grid(nblocks);
+    dim3 block(SW_TI, BatchTiles<Real>::THREADS / SW_TI), grid(nblocks);
     if (with_norm)
         batch_kernel<Real, true><<<grid, block, 0, s>>>(cavs, items, nitems, parity);
     else

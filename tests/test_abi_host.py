@@ -218,8 +218,20 @@ def test_batch_validation():
     narrow.ti = 32
     assert C.cavity_batch_table_bytes([narrow]) > C.cavity_batch_table_bytes([_member((40, 8, 9))])
     assert C.cavity_workspace_bytes(C.Grid(40, 8, 9)) == 64 + 2 * 9 * 5 * 8
-    # 40 x 24: 3 wide (64 x 8), 4 narrow (32 x 16) and 6 FP32 step (32 x 8) tiles
-    assert C.cavity_workspace_bytes(C.Grid(40, 24, 9)) == 64 + 6 * 9 * 5 * 8
+    # FP64 40 x 24: 3 wide (64 x 8) and 4 narrow (32 x 16) tiles
+    assert C.cavity_workspace_bytes(C.Grid(40, 24, 9)) == 64 + 4 * 9 * 5 * 8
+    # FP32 40 x 24: 6 tiles of 32 x 8 (step and wide batch tile), 6 of 16 x 16
+    assert C.cavity_workspace_bytes(C.Grid(40, 24, 9, dtype=1)) == 64 + 6 * 9 * 5 * 8
+    # FP32 40 x 8: 2 tiles of 32 x 8, 3 narrow ones of 16 x 16
+    assert C.cavity_workspace_bytes(C.Grid(40, 8, 9, dtype=1)) == 64 + 3 * 9 * 5 * 8
+    # the tile widths are per element type: FP32 takes 32 and 16, not 64
+    f32 = [_member((40, 8, 9), dtype=1) for _ in range(3)]
+    f32[0].ti, f32[1].ti, f32[2].ti = 32, 16, 64
+    assert C.cavity_batch_table_bytes(f32[:1]) > 0 and C.cavity_batch_table_bytes(f32[1:2]) > 0
+    assert C.cavity_batch_table_bytes(f32[2:]) == 0
+    assert build(f32[2:]) == C.CAV_EINVAL
+    assert C.batch_tile(1, 0) == (32, 8) and C.batch_tile(1, 16) == (16, 16)
+    assert C.batch_tile(0, 0) == (64, 8) and C.batch_tile(0, 32) == (32, 16)
     assert build(ok, tb=16) == C.CAV_ESIZE                               # table too small
     bad = _lib.CavBatch(None, 1, 1, 0, 0, 1)
     assert L.cavity_batch_step(ctypes.byref(bad), 1, 0, None) == C.CAV_EINVAL
