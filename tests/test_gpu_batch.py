@@ -164,3 +164,37 @@ def test_batch_member_with_hot_wall_field(C):
     uniform = C.Cavity(C.Grid(*n), C.Params(Ra=1e5)).init(5)
     uniform.step(7)
     assert not np.array_equal(interior(C, g, uniform.q), interior(C, g, cav.q))
+
+
+def test_batch96_workload_matches_single_runs(C):
+    """The timed batched workload (96 FP32 cavities, edges 24..96, Ra 1e3..1e6)
+    with the autotuned tile shapes and k chunks, 100 steps replayed from one
+    HIP graph: sampled members (every edge, the lowest and highest Ra) come
+    out bit-identical to advancing each alone with cavity_step."""
+    import torch
+    from paper_2006_02602_amd import autotune
+    from paper_2006_02602_amd.configs import batch_workload
+    say("batch96 workload x100 (graph)")
+    wl = batch_workload()
+    shapes = autotune.tune_shapes([e for e, _, _ in wl], C.CAV_F32, cache_path="/tmp/cavity_autotune.json")
+    b = C.Batch([(C.Grid.cube(e, C.CAV_F32), C.Params(Ra=ra), shapes[e][1], shapes[e][0]) for e, ra, _ in wl])
+    b.init([s for _, _, s in wl])
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        gr = b.graph(100, stream=st)
+        gr.launch(stream=st)
+        st.synchronize()
+        gr.destroy()
+    pick = {}
+    for m, (e, ra, _) in enumerate(wl):
+        pick.setdefault(e, m)
+    pick["lo"] = min(range(len(wl)), key=lambda m: wl[m][1])
+    pick["hi"] = max(range(len(wl)), key=lambda m: wl[m][1])
+    for m in sorted(set(pick.values())):
+        e, ra, s = wl[m]
+        g = C.Grid.cube(e, C.CAV_F32)
+        cav = C.Cavity(g, C.Params(Ra=ra)).init(s)
+        cav.step(100)
+        say("  member", m, "edge", e, "Ra %.3g" % ra, "tile", C.batch_tile(C.CAV_F32, shapes[e][0]), "kc", shapes[e][1])
+        assert np.array_equal(interior(C, g, b.state(m)), interior(C, g, cav.q)), (m, e, ra)
+        assert all(np.isfinite(b.norms(m)))

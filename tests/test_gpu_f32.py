@@ -160,3 +160,47 @@ def test_nusselt_against_oracle(C, dtype):
     P.interior(cond)[4][:] = 1.0 - x
     put_state(C, g, cav.q, cond)
     assert abs(cav.nusselt() - 1.0) < (1e-13 if dtype == 0 else 1e-5)
+
+
+def test_f32_full_size_against_oracle(C):
+    """The timed FP32 workload's grid and launch (384^3, Ra 1e6: 32 x 8
+    tiles, k chunks from the occupancy query): 4 steps against the FP64
+    oracle from the same (rounded) start, per field."""
+    say("f32 vs oracle 384^3 x4")
+    n = (384, 384, 384)
+    P, g, prm = problem(C, n, 1e6, C.CAV_F32)
+    q0 = O.init(P, 3, 1e-3).astype(np.float32).astype(np.float64)
+    ref = q0.copy()
+    nref = O.step(P, ref, 4)
+    cav = C.Cavity(g, prm)
+    put_state(C, g, cav.q, q0)
+    del q0
+    cav.step(4)
+    e = rel_err(P.interior(get_state(C, g, cav.q)), P.interior(ref))
+    say("  per-field rel err (p u v w T):", ["%.2e" % x for x in e])
+    assert max(e) <= TOL_F32, e
+    np.testing.assert_allclose(np.array(cav.norms()), nref, rtol=1e-3)
+
+
+def test_f32_mirror_symmetry_full_size(C):
+    """384^3 FP32, Ra 1e6, the timed 100 steps: a start mirror-symmetric in
+    y (v odd, the rest even) stays symmetric bit for bit; the stencil pairs
+    its operands commutatively, so this holds in FP32 as in FP64."""
+    say("f32 mirror 384^3 x100")
+    n = (384, 384, 384)
+    P, g, prm = problem(C, n, 1e6, C.CAV_F32)
+    q = O.init(P, 2, 1e-3)
+    I = P.interior(q)
+    half = P.nj // 2
+    for f in range(5):
+        s = -1.0 if f == 2 else 1.0
+        I[f][:, P.nj - half:, :] = s * I[f][:, :half, :][:, ::-1, :]
+    O.apply_bc(P, q)
+    cav = C.Cavity(g, prm)
+    put_state(C, g, cav.q, q.astype(np.float32).astype(np.float64))
+    del q, I
+    cav.step(100)
+    J = P.interior(get_state(C, g, cav.q))
+    for f in range(5):
+        s = -1.0 if f == 2 else 1.0
+        assert np.array_equal(J[f], s * J[f][:, ::-1, :]), O.FIELDS[f]
