@@ -136,15 +136,15 @@ def f32_leg(C, torch, steps):
 
 def batch_leg(C, torch, steps):
     """The batched form: 96 FP32 cubes of uneven edges and Rayleigh numbers,
-    tile shape and k chunk per edge and the block count from the autotuner,
-    `steps` steps replayed from one HIP graph."""
+    tile shape and k chunk per edge and the block count tuned on the whole
+    batch (autotune.tune_batch), `steps` steps replayed from one HIP graph."""
     from paper_2006_02602_amd import autotune
     from paper_2006_02602_amd.configs import batch_workload
     wl = batch_workload()
-    shapes = autotune.tune_shapes([e for e, _, _ in wl], C.CAV_F32, cache_path="/tmp/cavity_autotune.json")
-    b = C.Batch([(C.Grid.cube(e, C.CAV_F32), C.Params(Ra=ra), shapes[e][1], shapes[e][0]) for e, ra, _ in wl])
+    b = C.Batch([(C.Grid.cube(e, C.CAV_F32), C.Params(Ra=ra)) for e, ra, _ in wl])
     b.init([s for _, _, s in wl])
-    nb, tb = autotune.tune_blocks(b)
+    shapes, nb, tb = autotune.tune_batch(b, [e for e, _, _ in wl], C.CAV_F32,
+                                         cache_path="/tmp/cavity_autotune.json")
     b.init([s for _, _, s in wl])
     torch.cuda.synchronize()
     st = torch.cuda.Stream()
@@ -164,7 +164,8 @@ def batch_leg(C, torch, steps):
             "autotuned_tile_and_kc_per_edge": {str(k): {"tile": "%dx%d" % C.batch_tile(C.CAV_F32, v[0]), "kc": v[1]}
                                                for k, v in shapes.items()},
             "autotuned_blocks": nb,
-            "block_timings_ms": {str(k): v for k, v in tb.items()},
+            "block_timings_ms": tb.get("blocks", {}),
+            "tuning_trials": len([k for k in tb if k != "blocks"]),
             "bytes_per_step_algorithmic": 40 * b.cells,
             "GBs_algorithmic": 40 * b.cells / (dt / steps) / 1e9, "norms_finite": norms_ok}
 

@@ -391,6 +391,24 @@ class Batch:
     def __len__(self):
         return len(self.grids)
 
+    def retile(self, shapes) -> "Batch":
+        """Rebuild the work list with (kc, ti) per member, keeping every
+        member's state, workspace and the parity."""
+        import torch
+        cm = [CavBatchMember(m.grid, m.params, m.q, m.q_tmp, m.ws, m.ws_bytes, int(kc), int(ti))
+              for m, (kc, ti) in zip(self._members, shapes)]
+        nb = cavity_batch_table_bytes(cm)
+        if nb == 0:
+            raise CavError(CAV_EINVAL, "invalid batch members")
+        if nb > self.table.numel():
+            self.table = torch.zeros(nb, dtype=torch.uint8, device=self.table.device)
+        parity = self.handle.parity
+        self.handle = cavity_batch_build(cm, self.table)
+        self.handle.parity = parity
+        self._members = cm
+        self.kcs = [int(kc) for kc, _ in shapes]
+        return self
+
     @property
     def cells(self) -> int:
         return int(self.handle.cells)

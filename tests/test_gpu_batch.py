@@ -168,20 +168,25 @@ def test_batch_member_with_hot_wall_field(C):
 
 def test_batch96_workload_matches_single_runs(C):
     """The timed batched workload (96 FP32 cavities, edges 24..96, Ra 1e3..1e6)
-    with the autotuned tile shapes and k chunks, 100 steps replayed from one
-    HIP graph: sampled members (every edge, the lowest and highest Ra) come
-    out bit-identical to advancing each alone with cavity_step."""
+    with the tile shapes, k chunks and block count tuned on the whole batch,
+    100 steps replayed from one HIP graph: sampled members (every edge, the
+    lowest and highest Ra) come out bit-identical to advancing each alone
+    with cavity_step."""
     import torch
     from paper_2006_02602_amd import autotune
     from paper_2006_02602_amd.configs import batch_workload
     say("batch96 workload x100 (graph)")
     wl = batch_workload()
-    shapes = autotune.tune_shapes([e for e, _, _ in wl], C.CAV_F32, cache_path="/tmp/cavity_autotune.json")
-    b = C.Batch([(C.Grid.cube(e, C.CAV_F32), C.Params(Ra=ra), shapes[e][1], shapes[e][0]) for e, ra, _ in wl])
+    b = C.Batch([(C.Grid.cube(e, C.CAV_F32), C.Params(Ra=ra)) for e, ra, _ in wl])
+    b.init([s for _, _, s in wl])
+    shapes, nb, _ = autotune.tune_batch(b, [e for e, _, _ in wl], C.CAV_F32, cache_path="/tmp/cavity_autotune.json")
+    for e, (ti, kc) in shapes.items():
+        assert ti in autotune.ti_candidates(C.CAV_F32) and kc in autotune.KC_CANDIDATES and kc < e
+    assert nb in autotune.BLOCK_CANDIDATES
     b.init([s for _, _, s in wl])
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
-        gr = b.graph(100, stream=st)
+        gr = b.graph(100, nblocks=nb, stream=st)
         gr.launch(stream=st)
         st.synchronize()
         gr.destroy()
@@ -198,3 +203,21 @@ def test_batch96_workload_matches_single_runs(C):
         say("  member", m, "edge", e, "Ra %.3g" % ra, "tile", C.batch_tile(C.CAV_F32, shapes[e][0]), "kc", shapes[e][1])
         assert np.array_equal(interior(C, g, b.state(m)), interior(C, g, cav.q)), (m, e, ra)
         assert all(np.isfinite(b.norms(m)))
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_retile_keeps_states_and_parity(C, dtype):
+    """Rebuilding the work list between steps (other tile widths and k
+    chunks) changes nothing: 3 + 4 steps equal 7 steps, bit for bit."""
+    say("batch retile", dtype)
+    wide, narrow = C.BATCH_TILE_WIDTHS[dtype]
+    a = build(C, dtype).init(range(20, 20 + len(MEMBERS)))
+    b = build(C, dtype).init(range(20, 20 + len(MEMBERS)))
+    a.step(7)
+    b.step(3)
+    b.retile([(kc, narrow if m % 2 else wide) for m, kc in enumerate((4, 0, 8, 3, 16, 5))])
+    b.step(4)
+    assert b.handle.parity == a.handle.parity
+    for m, (n, _) in enumerate(MEMBERS):
+        g = C.Grid(*n, dtype=dtype)
+        assert np.array_equal(interior(C, g, a.state(m)), interior(C, g, b.state(m))), m
