@@ -9,8 +9,9 @@
 namespace cav {
 
 // ---------------------------------------------------------------------------
-// The sweep.  Block = one 64 x 8 tile of (i, j) columns (one wavefront per
-// j row, i along the lanes) marching over a chunk of k planes.  Plane k of
+// The sweep.  Block = one TI x TJ tile of (i, j) columns, i along the lanes
+// (64 x 8: one wavefront per j row; narrower tiles put 64 / TI rows in a
+// wavefront) marching over a chunk of k planes.  Plane k of
 // all five fields lives in LDS with its i/j halo (2 for p, 1 for the rest);
 // the k neighbours come from per-thread register queues (p: k-2..k+2,
 // others k-1..k+1).  The LDS planes are double-buffered: plane k+1 is
