@@ -251,3 +251,17 @@ def test_batch_workload_recipe():
     assert {e for e, _, _ in w} == set(BATCH_EDGES)
     assert all(1e3 <= ra < 1e6 for _, ra, _ in w)
     assert w == batch_workload()
+
+
+def test_largest_accepted_grids():
+    """One field must stay below 2^31 elements (32-bit cell offsets in the
+    kernels): the cubes on either side of that limit, sizes computed without
+    overflow (a 1278^3 FP64 state is 85 GB; q and q_tmp fit in 288 GB)."""
+    for dtype, ok, bad in ((0, 1278, 1279), (1, 1275, 1276)):
+        g = C.Grid.cube(ok, dtype)
+        L = C.cavity_layout(g)
+        assert L.sf < 2 ** 31 and C.cavity_state_elems(g) == 5 * L.sf > 2 ** 32
+        assert C.cavity_workspace_bytes(g) > 0
+        assert C.halo_buffer_bytes(g, C.Halo((2, 2, 2), (1, 2, 2, 2, 2))) > 0
+        b = C.Grid.cube(bad, dtype)
+        assert C.cavity_state_elems(b) == 0 and C.cavity_workspace_bytes(b) == 0
