@@ -262,6 +262,6 @@ def test_largest_accepted_grids():
         L = C.cavity_layout(g)
         assert L.sf < 2 ** 31 and C.cavity_state_elems(g) == 5 * L.sf > 2 ** 32
         assert C.cavity_workspace_bytes(g) > 0
-        assert C.halo_buffer_bytes(g, C.Halo((2, 2, 2), (1, 2, 2, 2, 2))) > 0
+        assert C.halo_buffer_bytes(g, C.Halo((3, 3, 3), (1, 2, 2, 2, 2))) > 0      # 3 divides both edges
         b = C.Grid.cube(bad, dtype)
         assert C.cavity_state_elems(b) == 0 and C.cavity_workspace_bytes(b) == 0
