@@ -324,7 +324,9 @@ int cavity_batch_step(cav_batch* batch, int32_t nsteps, int32_t nblocks, hipStre
  * instantiate it; *graph_exec receives the executable graph, which the
  * caller releases with cavity_batch_graph_destroy.  Each
  * cavity_batch_graph_launch replays the nsteps steps (the parity is
- * unchanged because nsteps is even). */
+ * unchanged because nsteps is even).  The graph holds the table's address
+ * and item count: rebuilding that table (cavity_batch_build into the same
+ * memory) invalidates it, so destroy the graph first. */
 int cavity_batch_graph_create(const cav_batch* batch, int32_t nsteps, int32_t nblocks,
                               hipStream_t stream, void** graph_exec);
 int cavity_batch_graph_launch(void* graph_exec, hipStream_t stream);

@@ -11,6 +11,7 @@ cavity of Xue & Roy (arXiv:2006.02602, Sec. 2-3) with the in-device halo
 pack/unpack of its "Optimized V1-V3" versions (Sec. 4.5).
 """
 import ctypes
+import weakref
 from dataclasses import dataclass, field
 from typing import Optional, Sequence, Tuple
 
@@ -387,14 +388,19 @@ class Batch:
             raise CavError(CAV_EINVAL, "invalid batch members")
         self.table = torch.zeros(nb, dtype=torch.uint8, device=device)
         self.handle = cavity_batch_build(cm, self.table)
+        self._graphs = weakref.WeakSet()
 
     def __len__(self):
         return len(self.grids)
 
     def retile(self, shapes) -> "Batch":
         """Rebuild the work list with (kc, ti) per member, keeping every
-        member's state, workspace and the parity."""
+        member's state, workspace and the parity.  A graph captured from the
+        old work list would replay it on the new table, so live graphs of
+        this batch must be destroyed first."""
         import torch
+        if any(gr.exec for gr in list(self._graphs)):
+            raise CavError(CAV_EINVAL, "destroy this batch's graphs before retiling it")
         cm = [CavBatchMember(m.grid, m.params, m.q, m.q_tmp, m.ws, m.ws_bytes, int(kc), int(ti))
               for m, (kc, ti) in zip(self._members, shapes)]
         nb = cavity_batch_table_bytes(cm)
@@ -444,6 +450,7 @@ class BatchGraph:
     def __init__(self, batch: Batch, nsteps: int, nblocks: int, stream):
         self.batch = batch
         self.exec = cavity_batch_graph_create(batch.handle, nsteps, nblocks, stream)
+        batch._graphs.add(self)
 
     def launch(self, stream=None) -> None:
         cavity_batch_graph_launch(self.exec, stream)

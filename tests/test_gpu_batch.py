@@ -218,6 +218,16 @@ def test_retile_keeps_states_and_parity(C, dtype):
     b.retile([(kc, narrow if m % 2 else wide) for m, kc in enumerate((4, 0, 8, 3, 16, 5))])
     b.step(4)
     assert b.handle.parity == a.handle.parity
+    # a live graph of the old work list blocks a rebuild of its table
+    import torch
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        gr = b.graph(2, stream=st)
+    st.synchronize()
+    with pytest.raises(C.CavError):
+        b.retile([(0, 0)] * len(MEMBERS))
+    gr.destroy()
+    b.retile([(0, 0)] * len(MEMBERS))
     for m, (n, _) in enumerate(MEMBERS):
         g = C.Grid(*n, dtype=dtype)
         assert np.array_equal(interior(C, g, a.state(m)), interior(C, g, b.state(m))), m
