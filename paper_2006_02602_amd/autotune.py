@@ -105,8 +105,10 @@ def tune_batch(batch, keys, dtype, steps=8, reps=3, passes=2, cache_path=None):
     starting shapes; the block count is tuned again at the end.
     Tuning in the full mix matters: alone, a small cavity wants short k
     chunks for parallelism, while in a batch the other members supply it and
-    short chunks only re-read their k halo planes.  The batch is stepped
-    while tuning and left with the chosen work list."""
+    short chunks only add work items, each paying its start-up (the centre
+    cell's star for the rescale, the k-queue prologue).  keys should
+    identify a member's grid (the cache is keyed by the multiset of keys).
+    The batch is stepped while tuning and left with the chosen work list."""
     distinct = sorted(set(keys))
     ckey = "v%d:%s:dtype%d:batch:%s" % (CACHE_VERSION, _arch(), dtype,
                                         ",".join("%s*%d" % (k, keys.count(k)) for k in distinct))
