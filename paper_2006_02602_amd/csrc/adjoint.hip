@@ -287,6 +287,19 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
     double Lw = lam.f[FW][o] + (R(R_WB, idx) + ctr * nu * aw);
     double Lt = lam.f[FT][o] + (aw + ctr * al * at);
 
+    // The x neighbours are the cells of the adjacent lanes (a wavefront holds
+    // consecutive cells, i fastest): their record values and u arrive by
+    // cross-lane moves, loads remain only at the wavefront's edges.  Every
+    // lane moves before any branch; a lane whose neighbour is no cell of
+    // this launch (it returned above) never uses the moved value.
+    const int wl = threadIdx.x & 63;
+    const double sh_in[7] = {au, av, aw, at, Xe[0], Bpe, q.f[FU][o]};
+    double sh_lo[7], sh_hi[7];
+#pragma unroll
+    for (int v = 0; v < 7; ++v) {
+        sh_lo[v] = __shfl_up(sh_in[v], 1, 64);
+        sh_hi[v] = __shfl_down(sh_in[v], 1, 64);
+    }
     const int pos[3] = {i, j, k};
     const int N[3] = {d.ni, d.nj, d.nk};
     const long long dstride[3] = {1, d.ni, (long long)d.ni * d.nj};
@@ -301,6 +314,12 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
         auto nb = [&](int sgn) {
             const long long m = idx + sgn * dstride[ax];
             Nb b;
+            if (ax == 0 && (sgn < 0 ? wl > 0 : wl < 63)) {
+                const double* S = sgn < 0 ? sh_lo : sh_hi;
+                b.au = S[0]; b.av = S[1]; b.aw = S[2]; b.at = S[3]; b.X = S[4]; b.Bp = S[5];
+                b.s = S[6] * H;
+                return b;
+            }
             b.au = R(R_AU, m);
             b.av = R(R_AV, m);
             b.aw = R(R_AW, m);
