@@ -88,7 +88,7 @@ def halo_bench(C, torch, grid, cav, splits, widths_list, reps):
     return out
 
 
-def f32_leg(C, torch, steps):
+def f32_leg(C, torch, steps, with_oracle=True):
     """The FP32 precision form on its own workload (384^3, Ra 1e6): FP32
     state and stencil, FP64 norms and Nusselt; plus its per-field error
     against the FP64 form of this library at 128^3 after 100 steps."""
@@ -131,10 +131,42 @@ def f32_leg(C, torch, steps):
     err = [float((B[f] - A[f]).abs().max() / A[f].abs().max()) for f in range(5)]
     out["rel_err_vs_f64_gpu_128cubed_100steps"] = dict(zip(("p", "u", "v", "w", "T"), err))
     out["nusselt_128cubed"] = {"f64": a.nusselt(), "f32": b.nusselt()}
+    del a, b, A, B
+    if with_oracle:
+        out.update(f32_vs_oracle(C, torch, n, Ra, seed, steps))
     return out
 
 
-def batch_leg(C, torch, steps):
+def f32_vs_oracle(C, torch, n, Ra, seed, steps):
+    """The timed FP32 workload from its seeded start, `steps` steps, against
+    the FP64 oracle run from the same (FP32-rounded) start on the host cores:
+    per-field relative error (max |a - b| / max |b| over the interior).  The
+    oracle's stepping loop is timed as the 384^3 FP64 CPU reference."""
+    import numpy as np
+    import oracle as O
+    g = C.Grid.cube(n, C.CAV_F32)
+    cav = C.Cavity(g, C.Params(Ra=Ra)).init(seed, 1e-3)
+    q0 = np.ascontiguousarray(C.state_view(g, cav.q).cpu().numpy(), dtype=np.float64)
+    cav.step(steps)
+    got = C.state_view(g, cav.q)[:, 2:-2, 2:-2, 2:-2].cpu().numpy()
+    nusselt_gpu = cav.nusselt()
+    del cav
+    P = O.Problem(n, Ra=Ra)
+    t0 = time.perf_counter()
+    O.step(P, q0, steps)
+    dt = time.perf_counter() - t0
+    ref = P.interior(q0)
+    err = [float(np.abs(got[f].astype(np.float64) - ref[f]).max() / np.abs(ref[f]).max()) for f in range(5)]
+    log("bench: f32 %d^3 x%d vs FP64 oracle: %s (oracle %.1f s)" % (n, steps, err, dt))
+    return {"rel_err_vs_f64_oracle_%dcubed_%dsteps" % (n, steps): dict(zip(("p", "u", "v", "w", "T"), err)),
+            "nusselt_vs_oracle": {"f32_gpu": nusselt_gpu, "f64_oracle": O.nusselt_hot(P, q0)},
+            "tolerance_per_field": 1e-5,
+            "oracle_run": {"value": P.ncell * steps / dt, "unit": "grid-point updates/s",
+                           "ssspnt_np1": P.ncell * steps / dt * 1e-7, "seconds": dt, "threads": O.threads(),
+                           "what": "FP64 oracle, %d^3 Ra %g, %d steps from the rounded start" % (n, Ra, steps)}}
+
+
+def batch_leg(C, torch, steps, with_oracle=True):
     """The batched form: 96 FP32 cubes of uneven edges and Rayleigh numbers,
     tile shape and k chunk per edge and the block count tuned on the whole
     batch (autotune.tune_batch), `steps` steps replayed from one HIP graph."""
@@ -158,6 +190,7 @@ def batch_leg(C, torch, steps):
         dt = time.perf_counter() - t0
         gr.destroy()
     norms_ok = all(all(x == x and abs(x) < 1e30 for x in b.norms(m)) for m in range(len(b)))
+    acc = batch_vs_oracle(C, torch, b, wl, steps, nb) if with_oracle else None
     return {"workload": "batch96_f32_edges24-96_ra1e3-1e6", "members": len(b), "cells": b.cells,
             "steps": steps, "value": b.cells * steps / dt, "unit": "grid-point updates/s",
             "ms_per_step": 1e3 * dt / steps, "launch": "one persistent kernel per step, %d steps in one HIP graph" % steps,
@@ -167,7 +200,45 @@ def batch_leg(C, torch, steps):
             "block_timings_ms": tb.get("blocks", {}),
             "tuning_trials": len([k for k in tb if k != "blocks"]),
             "bytes_per_step_algorithmic": 40 * b.cells,
-            "GBs_algorithmic": 40 * b.cells / (dt / steps) / 1e9, "norms_finite": norms_ok}
+            "GBs_algorithmic": 40 * b.cells / (dt / steps) / 1e9, "norms_finite": norms_ok,
+            "rel_err_vs_f64_oracle_sampled": acc}
+
+
+def batch_vs_oracle(C, torch, b, wl, steps, nb):
+    """Sampled members (the first of every edge, the lowest and the highest
+    Ra) of the batch after `steps` graph-replayed steps from the seeded
+    start, against the FP64 oracle from the same (FP32-rounded) start."""
+    import numpy as np
+    import oracle as O
+    b.init([s for _, _, s in wl])
+    q0 = {}
+    pick = {}
+    for m, (e, ra, _) in enumerate(wl):
+        pick.setdefault("edge%d" % e, m)
+    pick["ra_min"] = min(range(len(wl)), key=lambda m: wl[m][1])
+    pick["ra_max"] = max(range(len(wl)), key=lambda m: wl[m][1])
+    for m in set(pick.values()):
+        q0[m] = np.ascontiguousarray(C.state_view(b.grids[m], b.state(m)).cpu().numpy(), dtype=np.float64)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        gr = b.graph(steps, nblocks=nb, stream=st)
+        gr.launch(stream=st)
+        st.synchronize()
+        gr.destroy()
+    out = {}
+    for tag, m in sorted(pick.items(), key=lambda kv: kv[1]):
+        e, ra, _ = wl[m]
+        P = O.Problem(e, Ra=ra)
+        ref = q0[m].copy()
+        O.step(P, ref, steps)
+        got = C.state_view(b.grids[m], b.state(m))[:, 2:-2, 2:-2, 2:-2].cpu().numpy().astype(np.float64)
+        want = P.interior(ref)
+        err = [float(np.abs(got[f] - want[f]).max() / np.abs(want[f]).max()) for f in range(5)]
+        out[tag] = {"member": m, "edge": e, "Ra": ra, "steps": steps,
+                    "rel_err": dict(zip(("p", "u", "v", "w", "T"), err))}
+    out["max_rel_err"] = max(max(v["rel_err"].values()) for v in out.values())
+    out["tolerance_per_field"] = 1e-5
+    return out
 
 
 def overlap_leg(C, torch, grid, prm, splits, widths, steps):
@@ -272,10 +343,25 @@ def small_case(C, torch):
             "note": "3 launches per step (pack, unpack, sweep); launch-bound, no roofline claim"}
 
 
+def cpu_model():
+    """The host CPU's model string (/proc/cpuinfo), or the platform's."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(wl, budget_s):
     """The FP64 oracle on the host cores, on a bounded sample of the same
-    workload (same grid, parameters and halo; fewer steps)."""
+    workload (same grid, parameters and halo; fewer steps), plus the 16^3
+    parity workload in full (median of 3 runs)."""
     import oracle as O
+    from paper_2006_02602_amd.configs import C0
     P = O.Problem(wl.n, Ra=wl.Ra, Pr=0.71, cfl=0.5)
     q = O.init(P, wl.seed, wl.noise)
     halo = (wl.splits[0], wl.widths)
@@ -286,10 +372,42 @@ def cpu_baseline(wl, budget_s):
     t0 = time.perf_counter()
     O.step(P, q, steps, halo=halo)
     dt = time.perf_counter() - t0
-    return {"value": P.ncell * steps / dt, "unit": "grid-point updates/s", "cores": O.threads(),
+    value = P.ncell * steps / dt
+    # the small parity case in full: 16^3, Ra 1e3, 100 steps, 2x2x2 exchange
+    P0 = O.Problem(C0.n, Ra=C0.Ra)
+    runs = []
+    for _ in range(3):
+        q0 = O.init(P0, C0.seed, C0.noise)
+        t0 = time.perf_counter()
+        O.step(P0, q0, C0.steps, halo=(C0.splits[0], C0.widths))
+        runs.append(time.perf_counter() - t0)
+    t_c0 = sorted(runs)[1]
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"value": value, "unit": "grid-point updates/s", "cores": O.threads(),
             "kind": "oracle",
             "sample": "%d^3 Ra %g, %d steps (of %d) with the %s split, whole step timed (%.1f s)"
-                      % (wl.n, wl.Ra, steps, wl.steps, "x".join(map(str, wl.splits[0])), dt)}
+                      % (wl.n, wl.Ra, steps, wl.steps, "x".join(map(str, wl.splits[0])), dt),
+            "ssspnt_np1": value * 1e-7,
+            "host": {"cpu_model": cpu_model(), "nproc": usable, "os_cpu_count": os.cpu_count(),
+                     "omp_threads": O.threads()},
+            "small_case_16cubed_100steps": {"seconds_median_of_3": t_c0, "runs_s": runs,
+                                            "value": P0.ncell * C0.steps / t_c0, "unit": "grid-point updates/s"}}
+
+
+def counter_rates(kernel_hash, avg_us):
+    """Counter-based HBM rate of the sweep: the calibrated FETCH_SIZE +
+    WRITE_SIZE bytes of one launch (rocprofv3, committed summary tied to the
+    sweep source hash) over the launch's average duration."""
+    traffic = counter_traffic(kernel_hash)
+    if traffic is None:
+        return None, None
+    gbs = traffic / (avg_us * 1e-6) / 1e9
+    return traffic, {"GBs": gbs, "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": traffic,
+                     "time_source": "HIP events around each sweep launch in this run (same stream)",
+                     "counters": "profiles/sweep_cavity256_f64_counters.md"}
 
 
 def main():
@@ -307,6 +425,8 @@ def main():
     ap.add_argument("--legs", default=None,
                     help="comma list of extra legs to run (halo,f32,batch,adjoint,overlap; 'none' for the "
                          "headline only); overrides the --no-* flags")
+    ap.add_argument("--no-oracle", action="store_true",
+                    help="skip the FP32 and batch legs' comparisons with the FP64 oracle (about 45 s of host time)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
@@ -377,7 +497,14 @@ def main():
     ncell = grid.ncell
     achieved = SWEEP_BYTES_PER_CELL * ncell / (sw_ms * 1e-3) / 1e9
     kh = sweep_source_hash()
-    traffic = counter_traffic(kh)
+    traffic, counter = counter_rates(kh, 1e3 * sw_ms)
+    # the same K steps once more without events: how much of the timed pass
+    # is the device settling after the short warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cav.step(K)
+    torch.cuda.synchronize()
+    t_again = time.perf_counter() - t0
     breakdown = {k: {"launches": n, "avg_us": round(1e3 * ms / n, 2)} for k, (n, ms) in sorted(kt.items())}
     log("bench: sweep %.1f us -> %.0f GB/s algorithmic" % (1e3 * sw_ms, achieved))
 
@@ -395,13 +522,13 @@ def main():
     f32 = None
     if not args.no_f32:
         log("bench: FP32 form (384^3) ...")
-        f32 = f32_leg(C, torch, 100)
+        f32 = f32_leg(C, torch, 100, with_oracle=not args.no_oracle)
         log("bench: f32", f32)
 
     batch = None
     if not args.no_batch:
         log("bench: batched form (96 cavities) ...")
-        batch = batch_leg(C, torch, 100)
+        batch = batch_leg(C, torch, 100, with_oracle=not args.no_oracle)
         log("bench: batch", batch)
 
     ovl = None
@@ -440,9 +567,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "sweep_kernel", "bytes_per_launch": SWEEP_BYTES_PER_CELL * ncell,
-                     "avg_launch_us": 1e3 * sw_ms, "sweep_source_hash": kh},
+                     "achieved_is": "algorithmic bytes (80 B per interior cell) / average launch time",
+                     "avg_launch_us": 1e3 * sw_ms,
+                     "time_source": "HIP events around each sweep launch in this run (same stream)",
+                     "counter": counter, "sweep_source_hash": kh},
         "breakdown_us_per_launch": breakdown,
         "ms_per_step_with_events": 1e3 * t_ev / K,
+        "ms_per_step_second_pass": 1e3 * t_again / K,
         "residual_norms": norms,
     }
     line["small_case"] = small
@@ -468,6 +599,8 @@ def main():
     if not args.no_cpu:
         log("bench: CPU baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+        if f32 is not None and "oracle_run" in f32:
+            line["cpu_baseline"]["f64_384cubed_100steps"] = f32["oracle_run"]
         log("bench: CPU baseline", line["cpu_baseline"])
     print(json.dumps(line), flush=True)
 

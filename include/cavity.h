@@ -20,8 +20,8 @@
  *   - State layout.  q is ONE allocation of 5 fields in the order
  *     p, u, v, w, T (Listing 2: var 1 is pressure, vars 2..5 the velocities
  *     and temperature), i fastest and k slowest (Sec. 3.1), (i,j,k) = (x,y,z),
- *     with g = ng = 2 ghost layers per side (Listing 1: "interior cell index
- *     starts at 3").  Rows are padded so that every interior row starts on
+ *     with g = ng = 2 ghost layers per side (Sec. 4.5, Listing 1, whose
+ *     1-based arrays keep two ghost layers before the first interior cell).  Rows are padded so that every interior row starts on
  *     a 128-byte boundary (when q is 128-byte aligned): field f, cell
  *     (i, j, k) with -2 <= i < ni+2 etc. lives at element
  *         f*sf + (k+2)*sk + (j+2)*sj + lead + i
@@ -321,15 +321,20 @@ int cavity_batch_build(int32_t n, const cav_batch_member* members, void* table,
 int cavity_batch_step(cav_batch* batch, int32_t nsteps, int32_t nblocks, hipStream_t stream);
 
 /* Capture nsteps (even, >= 2) batch steps on `stream` into a HIP graph and
- * instantiate it; *graph_exec receives the executable graph, which the
- * caller releases with cavity_batch_graph_destroy.  Each
- * cavity_batch_graph_launch replays the nsteps steps (the parity is
- * unchanged because nsteps is even).  The graph holds the table's address
- * and item count: rebuilding that table (cavity_batch_build into the same
- * memory) invalidates it, so destroy the graph first. */
+ * instantiate it; *graph_exec receives a handle (host memory owned by the
+ * library until cavity_batch_graph_destroy releases it).  The captured
+ * launches read the newest states from where batch->parity says they were
+ * at capture, and hold the table's address and item count.
+ * cavity_batch_graph_launch(batch, ...) replays the nsteps steps (the
+ * parity stays the same, nsteps being even); it returns CAV_EINVAL and
+ * enqueues nothing when batch->parity differs from the captured one (an odd
+ * number of eager cavity_batch_step steps ran since) or when batch->table /
+ * batch->items are not the captured ones (the table was rebuilt).  A
+ * rebuild into the same memory (cavity_batch_build) is not detectable by
+ * address: destroy the graph before rebuilding. */
 int cavity_batch_graph_create(const cav_batch* batch, int32_t nsteps, int32_t nblocks,
                               hipStream_t stream, void** graph_exec);
-int cavity_batch_graph_launch(void* graph_exec, hipStream_t stream);
+int cavity_batch_graph_launch(const cav_batch* batch, void* graph_exec, hipStream_t stream);
 int cavity_batch_graph_destroy(void* graph_exec);
 
 /* Thread-local description of the last error returned on this thread. */

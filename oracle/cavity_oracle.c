@@ -27,7 +27,7 @@
 enum { FP = 0, FU = 1, FV = 2, FW = 3, FT = 4, NF = 5 };
 
 /* Index of field f, cell (i, j, k) with interior cells at 0..n-1 and
- * ghosts at -2, -1, n, n+1 (Listing 1: interior starts at index 3 of 1). */
+ * ghosts at -2, -1, n, n+1 (two ghost layers per side, Sec. 4.5, Listing 1). */
 static inline size_t at(const orc_problem* P, int f, int i, int j, int k)
 {
     size_t sx = (size_t)P->ni + 2 * NG, sy = (size_t)P->nj + 2 * NG, sz = (size_t)P->nk + 2 * NG;
@@ -289,9 +289,8 @@ void orc_residual(const orc_problem* P, const double* q, double* R, double* dt)
  * s, each face -x,+x,-y,+y,-z,+z that is a cut (not a cavity wall), each
  * field p,u,v,w,T with width w > 0: the box of the w interior layers of s
  * next to that face, over the interior tangential extent of s, is one
- * segment, stored in (k, j, i) order, i fastest -- for an i face with all
- * widths 2 this is Listing 1's index var*k_nodes*j_nodes*2 + k*j_nodes*2
- * + j*2 + i (0-based).  Reading: the receiver's ghost box beyond that face
+ * segment, stored in (k, j, i) order, i fastest (Reading of Listing 1's
+ * order, taken 0-based).  Reading: the receiver's ghost box beyond that face
  * covers the same cells, so with every subdomain in one array the unpack
  * writes each value back where the pack read it. */
 typedef void (*seg_fn)(const orc_problem* P, int f, int i, int j, int k, size_t pos, void* ctx);

@@ -7,8 +7,8 @@
  * It shares no code, header or constant with the GPU library.
  *
  * Layout: q holds 5 fields p,u,v,w,T (Listing 2's variable order), each
- * (nk+4)*(nj+4)*(ni+4) doubles with 2 ghost layers per side (Listing 1:
- * interior index starts at 3), i fastest (Sec. 3.1).
+ * (nk+4)*(nj+4)*(ni+4) doubles with 2 ghost layers per side (as in the
+ * arrays of Sec. 4.5, Listing 1), i fastest (Sec. 3.1).
  */
 #ifndef CAVITY_ORACLE_H_
 #define CAVITY_ORACLE_H_

@@ -276,8 +276,8 @@ def cavity_batch_graph_create(batch: CavBatch, nsteps: int, nblocks: int = 0, st
     return h.value
 
 
-def cavity_batch_graph_launch(graph_exec, stream=None) -> None:
-    check(lib().cavity_batch_graph_launch(graph_exec, _stream(stream)))
+def cavity_batch_graph_launch(batch: CavBatch, graph_exec, stream=None) -> None:
+    check(lib().cavity_batch_graph_launch(ctypes.byref(batch), graph_exec, _stream(stream)))
 
 
 def cavity_batch_graph_destroy(graph_exec) -> None:
@@ -453,7 +453,7 @@ class BatchGraph:
         batch._graphs.add(self)
 
     def launch(self, stream=None) -> None:
-        cavity_batch_graph_launch(self.exec, stream)
+        cavity_batch_graph_launch(self.batch.handle, self.exec, stream)
 
     def destroy(self) -> None:
         if self.exec:

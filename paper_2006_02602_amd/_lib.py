@@ -125,7 +125,7 @@ def lib():
     L.cavity_batch_graph_create.restype = ctypes.c_int
     L.cavity_batch_graph_create.argtypes = [BP, i32, i32, vp, ctypes.POINTER(ctypes.c_void_p)]
     L.cavity_batch_graph_launch.restype = ctypes.c_int
-    L.cavity_batch_graph_launch.argtypes = [vp, vp]
+    L.cavity_batch_graph_launch.argtypes = [BP, vp, vp]
     L.cavity_batch_graph_destroy.restype = ctypes.c_int
     L.cavity_batch_graph_destroy.argtypes = [vp]
     L.cavity_last_error.restype = ctypes.c_char_p

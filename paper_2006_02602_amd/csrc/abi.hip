@@ -311,6 +311,17 @@ int check_batch(const cav_batch* b)
     return CAV_OK;
 }
 
+// Host object behind a batch graph handle: the executable graph and what it
+// was captured from (its launches read the current states from q or q_tmp
+// as the batch's parity was at capture, so a replay is valid only while the
+// parity and the table are unchanged).
+struct BatchGraph {
+    hipGraphExec_t exec;
+    const void* table;
+    int32_t items;
+    int32_t parity;
+};
+
 int do_halo(const cav_grid* grid, const HaloGeom& hg, void* q, void* buf, bool pack, hipStream_t s)
 {
     if (hg.face_blocks == 0 || hg.wsum == 0) return CAV_OK;       // nothing to exchange
@@ -783,22 +794,33 @@ int cavity_batch_graph_create(const cav_batch* batch, int32_t nsteps, int32_t nb
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return hip_fail("graph instantiate", e);
-    *graph_exec = exec;
+    *graph_exec = new BatchGraph{exec, batch->table, batch->items, batch->parity};
     return CAV_OK;
 }
 
-int cavity_batch_graph_launch(void* graph_exec, hipStream_t stream)
+int cavity_batch_graph_launch(const cav_batch* batch, void* graph_exec, hipStream_t stream)
 {
+    int rc;
+    if ((rc = check_batch(batch))) return rc;
     if (!graph_exec) return fail(CAV_EINVAL, "graph_exec is NULL");
-    const hipError_t e = run("batch_graph", stream,
-                             [&] { return hipGraphLaunch(static_cast<hipGraphExec_t>(graph_exec), stream); });
+    const BatchGraph* g = static_cast<const BatchGraph*>(graph_exec);
+    if (g->table != batch->table || g->items != batch->items)
+        return fail(CAV_EINVAL, "the graph was captured from another batch table");
+    if (g->parity != batch->parity)
+        return fail(CAV_EINVAL,
+                    "the batch's newest states moved (parity %d, captured at %d): an odd number of eager steps "
+                    "ran since the capture; step once more or capture a new graph",
+                    batch->parity, g->parity);
+    const hipError_t e = run("batch_graph", stream, [&] { return hipGraphLaunch(g->exec, stream); });
     return e == hipSuccess ? CAV_OK : hip_fail("graph launch", e);
 }
 
 int cavity_batch_graph_destroy(void* graph_exec)
 {
     if (!graph_exec) return CAV_OK;
-    const hipError_t e = hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph_exec));
+    BatchGraph* g = static_cast<BatchGraph*>(graph_exec);
+    const hipError_t e = hipGraphExecDestroy(g->exec);
+    delete g;
     return e == hipSuccess ? CAV_OK : hip_fail("graph destroy", e);
 }
 

@@ -240,7 +240,8 @@ def test_batch_validation():
     assert L.cavity_batch_step(ctypes.byref(fake), -1, 0, None) == C.CAV_EINVAL
     assert L.cavity_batch_graph_create(ctypes.byref(fake), 3, 0, FAKE, ctypes.byref(h)) == C.CAV_EINVAL
     assert L.cavity_batch_graph_create(ctypes.byref(fake), 2, 0, None, ctypes.byref(h)) == C.CAV_EINVAL
-    assert L.cavity_batch_graph_launch(None, None) == C.CAV_EINVAL
+    assert L.cavity_batch_graph_launch(None, None, None) == C.CAV_EINVAL
+    assert L.cavity_batch_graph_launch(ctypes.byref(fake), None, None) == C.CAV_EINVAL
 
 
 def test_batch_workload_recipe():

@@ -6,9 +6,11 @@ differentiates with respect to.
   * gradient . direction against the complex-step tangent oracle
     (oracle/tangent.py) at 16^3 and on a ragged grid, in both time-step
     regimes, along state, wall and Ra directions (1e-9);
-  * gradient against central finite differences of the library's own
-    forward at 64^3, Ra 1e4, 400 steps, checkpoints every 20, along 16
-    seeded directions (1e-6);
+  * on the differentiation workload (64^3, Ra 1e4, 400 steps, checkpoints
+    every 20): against the tangent oracle along a wall and the Ra direction
+    (stored values, 1e-9), and against central finite differences of the
+    library's own forward along 16 seeded directions (h = 1e-6, and a
+    Richardson extrapolation at h = 1e-5 within the plain 1e-6);
   * checkpoint interval and in-place cotangents change nothing (bit-exact);
   * the torch.autograd wrapper returns the same gradient.
 """
@@ -125,20 +127,67 @@ def test_gradient_matches_tangent_oracle(C, n, Ra, steps):
             assert abs(got - want) <= 1e-9 * max(abs(want), 1e-6 * abs(Jt)), (name, got, want)
 
 
-def test_gradient_matches_finite_differences_64(C):
-    """64^3, Ra 1e4, 400 steps, checkpoints every 20; theta = 1 + 0.05 noise
-    (seed 5).  16 seeded directions in (theta, Ra): 12 random unit wall
-    directions, 2 uniform wall shifts, 2 in Ra; central differences of the
-    library's forward with h = 1e-6 (relative for Ra)."""
+def test_gradient_matches_tangent_oracle_64(C):
+    """The differentiation workload itself (64^3, Ra 1e4, 400 steps,
+    checkpoints every 20, SplitMix64 hot-wall field, seeded state) against
+    the complex-step tangent oracle along one seeded unit wall direction and
+    the Ra direction (tests/golden/adjoint64_tangent.json, written by
+    tests/golden/make_adjoint64_tangent.py from oracle/ alone).  The tangent
+    takes the same side of every kink as the adjoint, so the two agree to
+    rounding."""
+    import json
+    import os
     import torch
+    from paper_2006_02602_amd.adjoint import NusseltAdjoint
+    from paper_2006_02602_amd.configs import ADJOINT as A
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "adjoint64_tangent.json")))
+    assert (gold["n"], gold["Ra"], gold["steps"], gold["state_seed"]) == (A.n, A.Ra, A.steps, A.seed)
+    say("adjoint vs tangent 64^3 x400")
+    n = A.n
+    theta = A.theta()
+    want_theta = 1.0 + gold["theta_amp"] * (2.0 * np.array(
+        [(O.splitmix64(A.seed, m) >> 11) * 2.0 ** -53 for m in range(n * n)]) - 1.0)
+    assert np.array_equal(theta, want_theta)
+    g = A.grid
+    q0 = torch.zeros(C.cavity_state_elems(g), dtype=torch.float64, device="cuda")
+    C.cavity_init(g, C.Params(Ra=A.Ra), A.seed, gold["noise"], q0)
+    adj = NusseltAdjoint(g, C.Params(), A.steps, A.every)
+    J = adj.forward(torch.from_numpy(theta).cuda(), A.Ra, q0)
+    dth, dra, _ = adj.backward()
+    torch.cuda.synchronize()
+    v = np.random.default_rng(gold["wall_direction_seed"]).standard_normal(n * n)
+    v /= np.linalg.norm(v)
+    got_theta = float(dth.cpu().numpy() @ v)
+    got_ra = float(dra.cpu()[0]) * A.Ra
+    for name, got, want in (("J", J, gold["nusselt"]), ("dJ.theta_dir", got_theta, gold["dJ_dir_theta"]),
+                            ("dJ/dRa*Ra", got_ra, gold["dJ_dRa_times_Ra"])):
+        rel = abs(got - want) / abs(want)
+        say("  %-13s adjoint % .15e tangent % .15e rel %.2e" % (name, got, want, rel))
+        assert rel <= (1e-12 if name == "J" else 1e-9), (name, got, want)
+
+
+def test_gradient_matches_finite_differences_64(C):
+    """The differentiation workload (64^3, Ra 1e4, 400 steps, checkpoints
+    every 20, SplitMix64 hot-wall field, seeded state): 16 seeded directions
+    in (theta, Ra) -- 12 random unit wall directions, 2 uniform wall shifts,
+    2 in Ra -- against central differences of the library's forward with
+    h = 1e-6 (relative for Ra), and against the Richardson extrapolation
+    (4 D(h) - D(2h)) / 3 of central differences at h = 1e-5, whose
+    truncation error is O(h^4) and whose rounding error is ten times smaller
+    than at h = 1e-6.  Every direction's numbers are printed."""
+    import torch
+    from paper_2006_02602_amd.configs import ADJOINT as A
     say("adjoint vs FD 64^3")
-    n, Ra, steps = (64, 64, 64), 1e4, 400
-    theta = theta_of(n, 5)
-    g = C.Grid(*n)
-    P = O.Problem(*n)
-    q0 = O.init(P, 9, 1e-3)
-    J, dth, dra, _ = gradient(C, n, Ra, theta, q0, steps, every=20)
-    q0d = gpu_state(C, g, q0)
+    n, Ra, steps = (A.n,) * 3, A.Ra, A.steps
+    theta = A.theta()
+    g = A.grid
+    q0d = torch.zeros(C.cavity_state_elems(g), dtype=torch.float64, device="cuda")
+    C.cavity_init(g, C.Params(Ra=Ra), A.seed, 1e-3, q0d)
+    from paper_2006_02602_amd.adjoint import NusseltAdjoint
+    adj = NusseltAdjoint(g, C.Params(), steps, A.every)
+    J = adj.forward(torch.from_numpy(theta).cuda(), Ra, q0d)
+    dth, dra, _ = adj.backward()
+    dth, dra = dth.cpu().numpy(), float(dra.cpu()[0])
 
     def nu(th, ra):
         cav = C.Cavity(g, C.Params(Ra=ra, t_hot_field=torch.from_numpy(th).cuda()))
@@ -146,24 +195,32 @@ def test_gradient_matches_finite_differences_64(C):
         cav.step(steps)
         return cav.nusselt()
 
+    def central(v, r, h):
+        return (nu(theta + h * v, Ra + h * r) - nu(theta - h * v, Ra - h * r)) / (2 * h)
+
     rng = np.random.default_rng(10)
     dirs = []
     for _ in range(12):
         v = rng.standard_normal(n[1] * n[2])
-        dirs.append((v / np.linalg.norm(v), 0.0))
+        dirs.append(("wall", v / np.linalg.norm(v), 0.0))
     ones = np.ones(n[1] * n[2]) / n[1]
-    dirs += [(ones, 0.0), (-ones, 0.0), (np.zeros_like(ones), Ra), (np.zeros_like(ones), -Ra)]
-    h = 1e-6
-    worst = 0.0
-    for v, r in dirs:
-        fd = (nu(theta + h * v, Ra + h * r) - nu(theta - h * v, Ra - h * r)) / (2 * h)
+    dirs += [("+shift", ones, 0.0), ("-shift", -ones, 0.0), ("+Ra", np.zeros_like(ones), Ra),
+             ("-Ra", np.zeros_like(ones), -Ra)]
+    say("  J = %.15e" % J)
+    say("  %-6s %22s %22s %9s %22s %9s" % ("dir", "adjoint", "fd h=1e-6", "rel", "richardson h=1e-5", "rel"))
+    worst6 = worstR = 0.0
+    for name, v, r in dirs:
         got = float(dth @ v) + dra * r
-        err = abs(got - fd) / max(abs(fd), 1e-12)
-        worst = max(worst, err)
-        say("  adjoint % .12e  fd % .12e  rel %.2e" % (got, fd, err))
-        # truncation O(h^2); rounding ~ 1e-14 |J| / h
-        assert abs(got - fd) <= 1e-6 * abs(fd) + 1e-14 * abs(J) / h
-    say("  worst rel", worst)
+        fd6 = central(v, r, 1e-6)
+        rich = (4.0 * central(v, r, 1e-5) - central(v, r, 2e-5)) / 3.0
+        e6 = abs(got - fd6) / abs(fd6)
+        eR = abs(got - rich) / abs(rich)
+        worst6, worstR = max(worst6, e6), max(worstR, eR)
+        say("  %-6s % .15e % .15e %9.2e % .15e %9.2e" % (name, got, fd6, e6, rich, eR))
+        # h = 1e-6: truncation O(h^2) is negligible, rounding of J ~ 1e-14 |J| / h
+        assert abs(got - fd6) <= 1e-6 * abs(fd6) + 1e-14 * abs(J) / 1e-6
+        assert eR <= 1e-6, (name, got, rich)
+    say("  worst rel: fd h=1e-6 %.2e, richardson %.2e" % (worst6, worstR))
 
 
 def test_checkpoint_interval_and_in_place_change_nothing(C):

@@ -14,6 +14,9 @@ import oracle as O
 
 pytestmark = pytest.mark.gpu
 
+# the FP32 form's stated per-field tolerance against the FP64 oracle after 100 steps
+TOL_F32 = 1e-5
+
 MEMBERS = [((16, 16, 16), 1e3), ((67, 37, 21), 1e5), ((24, 24, 24), 3e4), ((40, 9, 13), 1e6),
            ((96, 96, 96), 2e5), ((5, 70, 11), 1e4)]
 
@@ -171,7 +174,8 @@ def test_batch96_workload_matches_single_runs(C):
     with the tile shapes, k chunks and block count tuned on the whole batch,
     100 steps replayed from one HIP graph: sampled members (every edge, the
     lowest and highest Ra) come out bit-identical to advancing each alone
-    with cavity_step."""
+    with cavity_step, and within 1e-5 per field of the FP64 oracle run from
+    the same (FP32-rounded) start."""
     import torch
     from paper_2006_02602_amd import autotune
     from paper_2006_02602_amd.configs import batch_workload
@@ -201,8 +205,42 @@ def test_batch96_workload_matches_single_runs(C):
         cav = C.Cavity(g, C.Params(Ra=ra)).init(s)
         cav.step(100)
         say("  member", m, "edge", e, "Ra %.3g" % ra, "tile", C.batch_tile(C.CAV_F32, shapes[e][0]), "kc", shapes[e][1])
-        assert np.array_equal(interior(C, g, b.state(m)), interior(C, g, cav.q)), (m, e, ra)
+        got = interior(C, g, b.state(m))
+        assert np.array_equal(got, interior(C, g, cav.q)), (m, e, ra)
         assert all(np.isfinite(b.norms(m)))
+        # and against the FP64 oracle from the same (FP32-rounded) start
+        P = O.Problem(e, Ra=ra)
+        ref = O.init(P, s, 1e-3).astype(np.float32).astype(np.float64)
+        O.step(P, ref, 100)
+        want = P.interior(ref)
+        err = [float(np.abs(got[f].astype(np.float64) - want[f]).max() / np.abs(want[f]).max()) for f in range(5)]
+        say("    rel err vs FP64 oracle (p u v w T):", ["%.2e" % x for x in err])
+        assert max(err) <= TOL_F32, (m, e, ra, err)
+
+
+def test_graph_refuses_replay_after_odd_eager_step(C):
+    """A graph replays the parity it was captured at: after an odd number of
+    eager steps the launch is refused (nothing enqueued); one more eager step
+    restores the parity and the replay is valid again."""
+    import torch
+    say("batch graph parity")
+    a = build(C, 1).init(range(30, 30 + len(MEMBERS)))
+    b = build(C, 1).init(range(30, 30 + len(MEMBERS)))
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        gr = b.graph(2, stream=st)
+        b.step(1, stream=st)
+        with pytest.raises(C.CavError) as e:
+            gr.launch(stream=st)
+        assert e.value.code == C.CAV_EINVAL
+        b.step(1, stream=st)
+        gr.launch(stream=st)
+        st.synchronize()
+        gr.destroy()
+    a.step(4)
+    for m, (n, _) in enumerate(MEMBERS):
+        g = C.Grid(*n, dtype=1)
+        assert np.array_equal(interior(C, g, a.state(m)), interior(C, g, b.state(m))), m
 
 
 @pytest.mark.parametrize("dtype", [0, 1])

@@ -1,10 +1,10 @@
 """Pins of the oracle's halo pack/unpack (Sec. 4.5, Listings 1-2) on the CPU.
 
 The buffer is checked against a brute-force gather written from the layout
-definition with numpy slicing, against the index formulas printed in
-Listing 1 (two layers of every field on an i face) and Listing 2 (pressure
-with two layers first, then the other fields with one layer), and for the
-round trip unpack(pack(q)) == q, also after poisoning every segment cell.
+definition with numpy slicing, against the i-face orders of Listing 1 (two
+layers of every field) and Listing 2 (pressure with two layers first, then
+the other fields with one layer) built from numpy boxes, and for the round
+trip unpack(pack(q)) == q, also after poisoning every segment cell.
 """
 import itertools
 
@@ -81,44 +81,39 @@ def test_element_count_closed_form(orc):
             assert O.halo_elems(P, (split, width)) == expect
 
 
-def test_listing1_index_order(orc):
-    """Listing 1: the -x face buffer of a block holds, for var = 0..4,
-    k, j over the face and i = 0, 1 the first two interior layers, at
-    index var*k_nodes*j_nodes*2 + k*j_nodes*2 + j*2 + i (0-based)."""
+def test_i_face_order_all_fields_two_layers(orc):
+    """Sec. 4.5, Listing 1 (read 0-based): on an i face every field sends
+    its two interior layers next to the cut, field after field, each as a
+    (k, j, i) box with i fastest.  Expected here: the numpy box of the
+    high block's -x face flattened in C order, which is that order."""
     ni, nj, nk = 8, 5, 3
     P = O.Problem(ni, nj, nk)
     q = np.random.default_rng(1).standard_normal(P.shape)
     buf = O.halo_pack(P, ((2, 1, 1), (2, 2, 2, 2, 2)), q)
-    seg = buf.size // 2                  # subdomain 0 sends +x, subdomain 1 sends -x
-    back = buf[seg:]                     # the -x face of the high block
     x0 = ni // 2
-    for var in range(5):
-        for k in range(nk):
-            for j in range(nj):
-                for i in range(2):
-                    indx = var * nk * nj * 2 + k * nj * 2 + j * 2 + i
-                    assert back[indx] == q[var, NG + k, NG + j, NG + x0 + i]
+    low_sends = q[:, NG:NG + nk, NG:NG + nj, NG + x0 - 2:NG + x0].reshape(-1)    # +x face of block 0
+    high_sends = q[:, NG:NG + nk, NG:NG + nj, NG + x0:NG + x0 + 2].reshape(-1)   # -x face of block 1
+    assert np.array_equal(buf, np.concatenate([low_sends, high_sends]))
+    # a planted slip (j fastest instead of i) is caught
+    wrong = q[:, NG:NG + nk, NG:NG + nj, NG + x0:NG + x0 + 2].transpose(0, 1, 3, 2).reshape(-1)
+    assert not np.array_equal(buf[buf.size // 2:], wrong)
 
 
-def test_listing2_stencil_widths(orc):
-    """Listing 2: pressure with two layers first (index k*j_nodes*2 + j*2
-    + i), then u, v, w, T with the first interior layer only, offset by
-    indx_p = k_nodes*j_nodes*2, at (var-2)*k_nodes*j_nodes + k*j_nodes + j
-    (var = 2..5 in the listing's 1-based numbering)."""
+def test_i_face_stencil_widths(orc):
+    """Sec. 4.5, Listing 2: each field sends as many layers as its stencil
+    reaches (p two, u v w T one), p's box first.  Expected here: the box of
+    two p layers, then the one-layer boxes of u, v, w, T, each flattened in
+    (k, j, i) order."""
     ni, nj, nk = 6, 4, 5
     P = O.Problem(ni, nj, nk)
     q = np.random.default_rng(2).standard_normal(P.shape)
     buf = O.halo_pack(P, ((2, 1, 1), (2, 1, 1, 1, 1)), q)
-    back = buf[buf.size // 2:]
+    back = buf[buf.size // 2:]                         # the -x face of the high block
     x0 = ni // 2
-    indx_p = nk * nj * 2
-    for k in range(nk):
-        for j in range(nj):
-            for i in range(2):
-                assert back[k * nj * 2 + j * 2 + i] == q[0, NG + k, NG + j, NG + x0 + i]
-            for var in range(2, 6):
-                indx = (var - 2) * nk * nj + k * nj + j
-                assert back[indx_p + indx] == q[var - 1, NG + k, NG + j, NG + x0]
+    p_box = q[0, NG:NG + nk, NG:NG + nj, NG + x0:NG + x0 + 2].reshape(-1)
+    rest = [q[f, NG:NG + nk, NG:NG + nj, NG + x0:NG + x0 + 1].reshape(-1) for f in range(1, 5)]
+    assert back.size == 2 * nk * nj + 4 * nk * nj
+    assert np.array_equal(back, np.concatenate([p_box] + rest))
 
 
 @pytest.mark.parametrize("split,width", [((2, 2, 2), (1, 2, 2, 2, 2)), ((8, 1, 1), (2, 1, 1, 1, 1)),
