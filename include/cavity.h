@@ -171,6 +171,32 @@ int cavity_step(const cav_grid* grid, const cav_params* prm, const cav_halo* hal
                 void* halo_buf, size_t halo_bytes, int32_t nsteps,
                 hipStream_t stream);
 
+/* Largest number of sweep blocks whose norm partials cavity_step_noalloc's
+ * static scratch holds (5 doubles each: 1.25 MiB per device). */
+#define CAV_NOALLOC_MAX_SWEEP_BLOCKS 32768
+
+/* cavity_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * same kernels, launches and results as cavity_step, with no workspace
+ * argument.  The per-block norm partials live in a static device array of
+ * the library (CAV_NOALLOC_MAX_SWEEP_BLOCKS blocks), one per device, held
+ * until the process ends; the call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine; it never records timing events),
+ * and looks the array's address up on its first call on each device.
+ * norms: device, 5 doubles (p, u, v, w, T), written with the residual L2
+ * norms of the last step; or NULL, which skips the norm pass.
+ * Every call on one device shares that device's array, and every sweep
+ * that computes norms overwrites its own partials first, so nothing needs
+ * clearing between calls; two calls that overlap in time on one device
+ * (on different streams, or from several threads) race on it and must
+ * not be issued.  CAV_ESIZE when norms != NULL and the grid's sweep needs
+ * more blocks than the array holds (every cube up to the largest accepted
+ * grid fits; only very flat grids exceed it).  Other arguments and errors
+ * as for cavity_step. */
+int cavity_step_noalloc(const cav_grid* grid, const cav_params* prm, const cav_halo* halo,
+                        void* q, void* q_tmp, void* halo_buf, size_t halo_bytes,
+                        double* norms, int32_t nsteps, hipStream_t stream);
+
 /* cavity_step with the interior/exterior split of Sec. 4.7: per step the
  * exchange (halo_pack, halo_unpack) runs on comm_stream while the cells
  * whose stars reach no unpacked cell (the interior) are updated on

@@ -182,6 +182,23 @@ def cavity_step(grid, params, halo, q, q_tmp, ws, halo_buf, nsteps: int, stream=
                             int(nsteps), _stream(stream)))
 
 
+def cavity_step_noalloc(grid, params, halo, q, q_tmp, halo_buf, norms, nsteps: int, stream=None) -> None:
+    """cavity_step with its norm partials in the library's static device
+    array (no workspace; the call allocates nothing).  norms: a device
+    tensor of 5 float64 written with the last step's residual norms, or
+    None to skip them."""
+    qp, _ = _ptr(q)
+    tp, _ = _ptr(q_tmp)
+    bp, bb = _ptr(halo_buf)
+    npt, nb = _ptr(norms)
+    if npt is not None and nb < 5 * 8:
+        raise ValueError("norms must hold 5 float64 values")
+    h = _halo(halo)
+    check(lib().cavity_step_noalloc(ctypes.byref(_grid(grid)), ctypes.byref(_params(params)),
+                                    ctypes.byref(h) if h is not None else None, qp, tp, bp, bb, npt,
+                                    int(nsteps), _stream(stream)))
+
+
 def cavity_step_overlap(grid, params, halo, q, q_tmp, ws, halo_buf, nsteps: int, stream=None,
                         comm_stream=None) -> None:
     """cavity_step with the interior sweep overlapping the exchange on

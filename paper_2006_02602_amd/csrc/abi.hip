@@ -16,6 +16,12 @@
 
 using namespace cav;
 
+// Scratch of cavity_step_noalloc: 5 FP64 norm partials per sweep block, for
+// up to CAV_NOALLOC_MAX_SWEEP_BLOCKS blocks (1.25 MiB).  One copy per device,
+// held until the process ends; every call on a device shares it.
+constexpr int NOALLOC_MAX_BLOCKS = CAV_NOALLOC_MAX_SWEEP_BLOCKS;
+static __device__ __align__(256) double scratch[(size_t)NOALLOC_MAX_BLOCKS * NF];
+
 namespace {
 
 thread_local char g_err[512] = "";
@@ -322,40 +328,46 @@ struct BatchGraph {
     int32_t parity;
 };
 
-int do_halo(const cav_grid* grid, const HaloGeom& hg, void* q, void* buf, bool pack, hipStream_t s)
+int do_halo(const cav_grid* grid, const HaloGeom& hg, void* q, void* buf, bool pack, hipStream_t s,
+            bool timed = true)
 {
     if (hg.face_blocks == 0 || hg.wsum == 0) return CAV_OK;       // nothing to exchange
     const Dims d = dims_of(grid);
-    hipError_t e = run(pack ? "halo_pack" : "halo_unpack", s, [&] {
+    auto launch = [&] {
         return grid->dtype == CAV_F32
                    ? launch_halo<float>(d, hg, state_of<float>(q, d), static_cast<float*>(buf), pack, s)
                    : launch_halo<double>(d, hg, state_of<double>(q, d), static_cast<double*>(buf), pack, s);
-    });
+    };
+    hipError_t e = timed ? run(pack ? "halo_pack" : "halo_unpack", s, launch) : launch();
     return e == hipSuccess ? CAV_OK : hip_fail(pack ? "halo_pack launch" : "halo_unpack launch", e);
 }
 
-// The pseudo-time steps of cavity_step in element type Real.
+// The pseudo-time steps of cavity_step in element type Real.  The last
+// sweep writes 5 norm partials per block into `partials` and the finalize
+// reduces them into norms[0..4]; with norms == NULL the norm pass is
+// skipped.  `timed` allows the event timing (which creates events); the
+// allocation-free entry point passes false.
 template <typename Real>
 int step_impl(const cav_grid* grid, const cav_params* prm, const cav_halo* halo, const HaloGeom& hg, void* q,
-              void* q_tmp, void* ws, void* halo_buf, int32_t nsteps, hipStream_t stream)
+              void* q_tmp, double* partials, double* norms, void* halo_buf, int32_t nsteps, hipStream_t stream,
+              bool timed = true)
 {
     int rc;
     const Dims d = dims_of(grid);
     const Coef c = coef_of(grid, prm);
     const SweepGeom g = step_geom<Real>(d, device_slots());
-    double* wsd = static_cast<double*>(ws);
-    double* partials = reinterpret_cast<double*>(static_cast<char*>(ws) + WS_HEAD);
+    auto go = [&](const char* name, auto&& launch) { return timed ? run(name, stream, launch) : launch(); };
     void* cur = q;
     void* nxt = q_tmp;
     hipError_t e;
     for (int n = 0; n < nsteps; ++n) {
         // the wall ghosts are derived inside the sweep; no separate pass
         if (halo) {
-            if ((rc = do_halo(grid, hg, cur, halo_buf, true, stream))) return rc;
-            if ((rc = do_halo(grid, hg, cur, halo_buf, false, stream))) return rc;
+            if ((rc = do_halo(grid, hg, cur, halo_buf, true, stream, timed))) return rc;
+            if ((rc = do_halo(grid, hg, cur, halo_buf, false, stream, timed))) return rc;
         }
-        const bool last = n == nsteps - 1;
-        e = run(last ? "sweep_norm" : "sweep", stream, [&] {
+        const bool last = n == nsteps - 1 && norms;
+        e = go(last ? "sweep_norm" : "sweep", [&] {
             return launch_sweep<Real>(d, c, g, cstate_of<Real>(cur, d), state_of<Real>(nxt, d), partials, last,
                                       stream);
         });
@@ -364,14 +376,65 @@ int step_impl(const cav_grid* grid, const cav_params* prm, const cav_halo* halo,
         cur = nxt;
         nxt = t;
     }
-    const double ncell = (double)d.ni * d.nj * d.nk;
-    e = run("norm_finalize", stream, [&] { return launch_norm_finalize(partials, g.nblocks, ncell, wsd, stream); });
-    if (e != hipSuccess) return hip_fail("norm finalize launch", e);
+    if (norms) {
+        const double ncell = (double)d.ni * d.nj * d.nk;
+        e = go("norm_finalize", [&] { return launch_norm_finalize(partials, g.nblocks, ncell, norms, stream); });
+        if (e != hipSuccess) return hip_fail("norm finalize launch", e);
+    }
     if (cur != q) {
         const size_t bytes = (size_t)NF * field_elems(d) * sizeof(Real);
-        e = run("copy", stream, [&] { return hipMemcpyAsync(q, cur, bytes, hipMemcpyDeviceToDevice, stream); });
+        e = go("copy", [&] { return hipMemcpyAsync(q, cur, bytes, hipMemcpyDeviceToDevice, stream); });
         if (e != hipSuccess) return hip_fail("state copy", e);
     }
+    return CAV_OK;
+}
+
+// Argument checks shared by cavity_step and cavity_step_noalloc (everything
+// but the workspace).
+int check_step(const cav_grid* grid, const cav_params* prm, const cav_halo* halo, const void* q, const void* q_tmp,
+               const void* halo_buf, size_t halo_bytes, int32_t nsteps, HaloGeom* hg)
+{
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_params(prm))) return rc;
+    if (nsteps < 0) return fail(CAV_EINVAL, "nsteps = %d must be >= 0", nsteps);
+    if (!q || !q_tmp) return fail(CAV_EINVAL, "q and q_tmp must not be NULL");
+    if (q == q_tmp) return fail(CAV_EINVAL, "q and q_tmp must be distinct buffers");
+    if (halo) {
+        if ((rc = check_halo(grid, halo, hg))) return rc;
+        const size_t need = halo_elems(*hg) * (size_t)elem_size(grid->dtype);
+        if (need && !halo_buf) return fail(CAV_EINVAL, "halo_buf is NULL");
+        if (halo_bytes < need) return fail(CAV_ESIZE, "halo_bytes %zu < required %zu", halo_bytes, need);
+    }
+    return CAV_OK;
+}
+
+// ---- the scratch of cavity_step_noalloc -------------------------------------
+// Its sweeps' per-block norm partials live in the file-scope array `scratch`
+// (declared above this namespace).  Host code never uses the array's name as
+// an address: on the host it is a stand-in, not device memory.  Each
+// device's address is looked up once with hipGetSymbolAddress, with that
+// device current, and kept in g_scratch_dev.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device).
+int scratch_of_current_device(double** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail("hipGetDevice", e);
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(CAV_EINVAL, "device %d beyond the %d supported", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail("hipGetSymbolAddress(scratch)", e);
+        if (!p) return fail(CAV_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_dev[dev];
     return CAV_OK;
 }
 
@@ -530,23 +593,38 @@ int cavity_step(const cav_grid* grid, const cav_params* prm, const cav_halo* hal
                 hipStream_t stream)
 {
     int rc;
-    if ((rc = check_grid(grid)) || (rc = check_params(prm))) return rc;
-    if (nsteps < 0) return fail(CAV_EINVAL, "nsteps = %d must be >= 0", nsteps);
-    if (!q || !q_tmp || !ws) return fail(CAV_EINVAL, "q, q_tmp and ws must not be NULL");
-    if (q == q_tmp) return fail(CAV_EINVAL, "q and q_tmp must be distinct buffers");
-    const Dims d = dims_of(grid);
+    HaloGeom hg;
+    if ((rc = check_step(grid, prm, halo, q, q_tmp, halo_buf, halo_bytes, nsteps, &hg))) return rc;
+    if (!ws) return fail(CAV_EINVAL, "ws must not be NULL");
     const size_t need_ws = ws_bytes_of(grid);
     if (ws_bytes < need_ws) return fail(CAV_ESIZE, "ws_bytes %zu < required %zu", ws_bytes, need_ws);
-    HaloGeom hg;
-    if (halo) {
-        if ((rc = check_halo(grid, halo, &hg))) return rc;
-        const size_t need = halo_elems(hg) * (size_t)elem_size(grid->dtype);
-        if (need && !halo_buf) return fail(CAV_EINVAL, "halo_buf is NULL");
-        if (halo_bytes < need) return fail(CAV_ESIZE, "halo_bytes %zu < required %zu", halo_bytes, need);
-    }
     if (nsteps == 0) return CAV_OK;
-    return grid->dtype == CAV_F32 ? step_impl<float>(grid, prm, halo, hg, q, q_tmp, ws, halo_buf, nsteps, stream)
-                                  : step_impl<double>(grid, prm, halo, hg, q, q_tmp, ws, halo_buf, nsteps, stream);
+    double* norms = static_cast<double*>(ws);
+    double* partials = reinterpret_cast<double*>(static_cast<char*>(ws) + WS_HEAD);
+    return grid->dtype == CAV_F32
+               ? step_impl<float>(grid, prm, halo, hg, q, q_tmp, partials, norms, halo_buf, nsteps, stream)
+               : step_impl<double>(grid, prm, halo, hg, q, q_tmp, partials, norms, halo_buf, nsteps, stream);
+}
+
+int cavity_step_noalloc(const cav_grid* grid, const cav_params* prm, const cav_halo* halo, void* q, void* q_tmp,
+                        void* halo_buf, size_t halo_bytes, double* norms, int32_t nsteps, hipStream_t stream)
+{
+    int rc;
+    HaloGeom hg;
+    if ((rc = check_step(grid, prm, halo, q, q_tmp, halo_buf, halo_bytes, nsteps, &hg))) return rc;
+    const SweepGeom g = grid->dtype == CAV_F32 ? step_geom<float>(dims_of(grid), device_slots())
+                                               : step_geom<double>(dims_of(grid), device_slots());
+    if (norms && g.nblocks > NOALLOC_MAX_BLOCKS)
+        return fail(CAV_ESIZE,
+                    "grid %d x %d x %d: its sweep runs %d blocks, whose norm partials exceed the static scratch "
+                    "of %d blocks (pass norms = NULL, or use cavity_step with a workspace)",
+                    grid->ni, grid->nj, grid->nk, g.nblocks, NOALLOC_MAX_BLOCKS);
+    double* partials = nullptr;
+    if ((rc = scratch_of_current_device(&partials))) return rc;
+    if (nsteps == 0) return CAV_OK;
+    return grid->dtype == CAV_F32
+               ? step_impl<float>(grid, prm, halo, hg, q, q_tmp, partials, norms, halo_buf, nsteps, stream, false)
+               : step_impl<double>(grid, prm, halo, hg, q, q_tmp, partials, norms, halo_buf, nsteps, stream, false);
 }
 
 int cavity_step_overlap(const cav_grid* grid, const cav_params* prm, const cav_halo* halo, void* q, void* q_tmp,

@@ -103,6 +103,34 @@ def test_step_zero_steps_is_a_no_op():
     assert _step_rc(nsteps=0) == C.CAV_OK
 
 
+def test_step_noalloc_validation():
+    """The allocation-free step checks its arguments as cavity_step does,
+    and refuses a grid whose sweep needs more norm-partial slots than its
+    static scratch holds (a flat 2 x 600000 x 2 grid: 75000 tiles of 64 x 8),
+    all before anything is enqueued."""
+    L = C.lib()
+    g = C.Grid(16, 16, 16).c()
+    p = C.Params().c()
+    h = C.Halo((2, 2, 2), (1, 2, 2, 2, 2)).c()
+    T2 = ctypes.c_void_p(0x2000)
+    need = C.halo_buffer_bytes(C.Grid(16, 16, 16), C.Halo((2, 2, 2), (1, 2, 2, 2, 2)))
+
+    def rc(grid=g, halo=None, q=FAKE, q_tmp=T2, buf=None, buf_bytes=0, norms=FAKE, nsteps=1):
+        return L.cavity_step_noalloc(ctypes.byref(grid), ctypes.byref(p), ctypes.byref(halo) if halo else None,
+                                     q, q_tmp, buf, buf_bytes, norms, nsteps, None)
+
+    assert rc(q=None) == C.CAV_EINVAL
+    assert rc(q_tmp=FAKE) == C.CAV_EINVAL
+    assert rc(nsteps=-1) == C.CAV_EINVAL
+    assert rc(halo=h, buf=None, buf_bytes=need) == C.CAV_EINVAL
+    assert rc(halo=h, buf=FAKE, buf_bytes=need - 8) == C.CAV_ESIZE
+    flat = C.Grid(2, 600000, 2).c()
+    assert rc(grid=flat) == C.CAV_ESIZE
+    assert "static scratch" in C.cavity_last_error()
+    assert _lib.CAV_NOALLOC_MAX_SWEEP_BLOCKS == int(re.search(r"CAV_NOALLOC_MAX_SWEEP_BLOCKS\s+(\d+)",
+                                                              open(HEADER).read()).group(1))
+
+
 def test_t_hot_field_must_be_a_float64_gpu_tensor():
     import torch
     with pytest.raises(ValueError):
