@@ -196,10 +196,17 @@ int check_halo(const cav_grid* g, const cav_halo* h, HaloGeom* out)
     hg.area[0] = (long long)hg.e[1] * hg.e[2];
     hg.area[1] = (long long)hg.e[0] * hg.e[2];
     hg.area[2] = (long long)hg.e[0] * hg.e[1];
-    long long amax = 0;
-    for (int a = 0; a < 3; ++a)
-        if (hg.P[a] > 1 && hg.area[a] > amax) amax = hg.area[a];
-    hg.face_blocks = (int)((amax + 255) / 256);
+    // the launch: for each axis, its cut faces (2 per cut and transverse
+    // subdomain pair) times the blocks one face needs
+    long long end = 0;
+    for (int a = 0; a < 3; ++a) {
+        hg.nface[a] = (int)(2LL * (hg.P[a] - 1) * (nsub / hg.P[a]));
+        const long long per_block = (long long)HALO_THREADS * HALO_ROWS;
+        hg.bpf[a] = hg.nface[a] > 0 ? (int)((hg.area[a] + per_block - 1) / per_block) : 0;
+        end += (long long)hg.nface[a] * hg.bpf[a];
+        if (end >= (1LL << 31)) return fail(CAV_EINVAL, "halo launch of %lld blocks is too large", end);
+        hg.blk_end[a] = (int)end;
+    }
     if (out) *out = hg;
     return CAV_OK;
 }
@@ -237,7 +244,7 @@ size_t ws_bytes_of(const Dims& d, bool f32)
     auto tiles = [&](int ti, int tj) { return (size_t)((d.ni + ti - 1) / ti) * ((d.nj + tj - 1) / tj); };
     size_t t = std::max(tiles(SW_TI, SW_TJ), tiles(batch_wide_ti(f32), batch_tj(f32, batch_wide_ti(f32))));
     t = std::max(t, tiles(batch_narrow_ti(f32), batch_tj(f32, batch_narrow_ti(f32))));
-    if (f32) t = std::max(t, tiles(F32_TI, F32_TJ));
+    t = std::max(t, f32 ? tiles(F32_TI, F32_TJ) : tiles(F64_TI, F64_TJ));
     return WS_HEAD + t * d.nk * NF * sizeof(double);
 }
 size_t ws_bytes_of(const cav_grid* g) { return ws_bytes_of(dims_of(g), g->dtype == CAV_F32); }
@@ -292,12 +299,13 @@ template <typename Real>
 hipError_t batch_launches(const cav_batch& b, int32_t nsteps, int nblocks, int parity, hipStream_t stream, bool timed)
 {
     const BatchCav* cavs = static_cast<const BatchCav*>(b.table);
-    const BatchItem* items = reinterpret_cast<const BatchItem*>(static_cast<const char*>(b.table) +
-                                                                align256(sizeof(BatchCav) * b.members));
+    const char* region = static_cast<const char*>(b.table) + align256(sizeof(BatchCav) * b.members);
+    const int* segs = reinterpret_cast<const int*>(region);
+    const BatchItem* items = reinterpret_cast<const BatchItem*>(region + BATCH_HEAD_BYTES);
     hipError_t e = hipSuccess;
     for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
         const bool last = n == nsteps - 1;
-        auto go = [&] { return launch_batch<Real>(cavs, items, b.items, parity, last, nblocks, stream); };
+        auto go = [&] { return launch_batch<Real>(cavs, segs, items, parity, last, nblocks, stream); };
         e = timed ? run(last ? "batch_norm" : "batch", stream, go) : go();
         parity ^= 1;
     }
@@ -331,7 +339,7 @@ struct BatchGraph {
 int do_halo(const cav_grid* grid, const HaloGeom& hg, void* q, void* buf, bool pack, hipStream_t s,
             bool timed = true)
 {
-    if (hg.face_blocks == 0 || hg.wsum == 0) return CAV_OK;       // nothing to exchange
+    if (hg.blk_end[2] == 0 || hg.wsum == 0) return CAV_OK;       // nothing to exchange
     const Dims d = dims_of(grid);
     auto launch = [&] {
         return grid->dtype == CAV_F32
@@ -771,7 +779,7 @@ size_t cavity_batch_table_bytes(int32_t n, const cav_batch_member* members)
         items += (size_t)member_geom(dims_of(&members[m].grid), members[m].kc, member_ti(members[m]),
                                      members[m].grid.dtype == CAV_F32).nblocks;
     }
-    return align256(sizeof(BatchCav) * n) + sizeof(BatchItem) * items;
+    return align256(sizeof(BatchCav) * n) + BATCH_HEAD_BYTES + sizeof(BatchItem) * items;
 }
 
 int cavity_batch_build(int32_t n, const cav_batch_member* members, void* table, size_t table_bytes, cav_batch* out,
@@ -815,12 +823,32 @@ int cavity_batch_build(int32_t n, const cav_batch_member* members, void* table, 
             work.push_back({{m, t}, ci * cj * ck});
         }
     }
-    // longest items first, so the persistent blocks finish together
-    std::stable_sort(work.begin(), work.end(), [](const Work& a, const Work& b) { return a.cost > b.cost; });
+    // Members with the longest items first (so the persistent blocks finish
+    // together), each member's tiles in tiling order; then the list is cut
+    // into BATCH_SEGS contiguous segments of about equal cost, one per XCD.
+    std::vector<long long> mcost(n, 0);
+    for (const Work& w : work) mcost[w.it.cav] = std::max(mcost[w.it.cav], w.cost);
+    std::stable_sort(work.begin(), work.end(), [&](const Work& a, const Work& b) {
+        return mcost[a.it.cav] > mcost[b.it.cav] || (mcost[a.it.cav] == mcost[b.it.cav] && a.it.cav < b.it.cav);
+    });
+    long long total = 0;
+    for (const Work& w : work) total += w.cost;
     std::vector<char> host(need, 0);
     std::memcpy(host.data(), cavs.data(), sizeof(BatchCav) * n);
-    BatchItem* items = reinterpret_cast<BatchItem*>(host.data() + align256(sizeof(BatchCav) * n));
-    for (size_t w = 0; w < work.size(); ++w) items[w] = work[w].it;
+    char* region = host.data() + align256(sizeof(BatchCav) * n);
+    int* segs = reinterpret_cast<int*>(region);
+    BatchItem* items = reinterpret_cast<BatchItem*>(region + BATCH_HEAD_BYTES);
+    static_assert((BATCH_SEGS + 1) * sizeof(int) <= BATCH_HEAD_BYTES, "segment bounds fit the head");
+    long long run = 0;
+    int seg = 1;
+    segs[0] = 0;
+    for (size_t w = 0; w < work.size(); ++w) {
+        items[w] = work[w].it;
+        run += work[w].cost;
+        // close segment `seg` once its share of the cost is reached
+        while (seg < BATCH_SEGS && run * BATCH_SEGS >= total * seg) segs[seg++] = (int)(w + 1);
+    }
+    while (seg <= BATCH_SEGS) segs[seg++] = (int)work.size();
     hipError_t e = hipMemcpyAsync(table, host.data(), need, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail("batch table upload", e);

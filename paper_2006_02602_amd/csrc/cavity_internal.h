@@ -72,6 +72,16 @@ SweepGeom sweep_geom(const Dims& d, int slots, int ti = SW_TI, int tj = SW_TJ);
 // wavefronts, so that three blocks stay resident per compute unit at that
 // kernel's register count (FP64 keeps SW_TI x SW_TJ, one block of eight).
 constexpr int F32_TI = 32, F32_TJ = 8;
+#ifndef CAV_F64_STEP_TJ
+#define CAV_F64_STEP_TJ 8
+#endif
+#ifndef CAV_F64_STEP_DEPTH
+#define CAV_F64_STEP_DEPTH 3
+#endif
+#ifndef CAV_F64_STEP_WAVES
+#define CAV_F64_STEP_WAVES 0
+#endif
+constexpr int F64_TI = 64, F64_TJ = CAV_F64_STEP_TJ;
 // Geometry of the step sweep for element type Real on `cus` compute units
 // (its tile, and the resident blocks per compute unit the occupancy query
 // reports).
@@ -91,8 +101,14 @@ struct HaloGeom {
     int wsum;                 // sum of widths
     int wpre[NF];             // exclusive prefix sums of widths
     long long area[3];        // face area of an i, j, k face
-    int face_blocks;          // blocks per (subdomain, face)
+    int nface[3];             // cut faces normal to i, j, k (both sides of every cut)
+    int bpf[3];               // blocks per face normal to i, j, k
+    int blk_end[3];           // end of each axis' block range in the launch (cumulative)
 };
+// Tangential cells one halo thread moves (all fields and layers of each),
+// HALO_ROWS of them 256 apart.
+constexpr int HALO_THREADS = 256;
+constexpr int HALO_ROWS = 4;
 
 // Tile shapes of the batched kernel, a wide and a narrow one per element
 // type, both of the type's block size: FP64 64 x 8 and 32 x 16 (512
@@ -118,6 +134,14 @@ struct BatchCav {
 struct BatchItem {
     int cav, tile;
 };
+// The work list is cut into BATCH_SEGS contiguous segments of about equal
+// cost, one per XCD: the items region of the table starts with the
+// BATCH_SEGS + 1 segment bounds (padded to BATCH_HEAD_BYTES), then the
+// items.  Blocks on XCD x (hardware ids dispatched round-robin over the 8
+// XCDs) walk only segment x, so neighbouring tiles of a member run on one
+// XCD and share its L2.
+constexpr int BATCH_SEGS = 8;
+constexpr int BATCH_HEAD_BYTES = 64;
 constexpr int WS_HEAD_DOUBLES = 8;        // norms (5), Nusselt, padding
 
 // Launchers (return hipGetLastError() of the launch); Real = double or float.
@@ -135,7 +159,7 @@ template <typename Real>
 hipError_t launch_halo(const Dims& d, const HaloGeom& h, StateT<Real> q, Real* buf, bool pack,
                        hipStream_t s);
 template <typename Real>
-hipError_t launch_batch(const BatchCav* cavs, const BatchItem* items, int nitems, int parity, bool with_norm,
+hipError_t launch_batch(const BatchCav* cavs, const int* segs, const BatchItem* items, int parity, bool with_norm,
                         int nblocks, hipStream_t s);
 hipError_t launch_batch_norms(const BatchCav* cavs, int members, hipStream_t s);
 template <typename Real>

@@ -25,15 +25,19 @@ namespace cav {
 // resident blocks per compute unit, whose barriers interleave).
 template <typename Real>
 struct StepTile {
-    static constexpr int TI = sizeof(Real) == 4 ? F32_TI : SW_TI;
-    static constexpr int TJ = sizeof(Real) == 4 ? F32_TJ : SW_TJ;
+    static constexpr int TI = sizeof(Real) == 4 ? F32_TI : F64_TI;
+    static constexpr int TJ = sizeof(Real) == 4 ? F32_TJ : F64_TJ;
     static constexpr int THREADS = TI * TJ;
+    // minimum waves per SIMD the compiler must fit (0: its own choice)
+    static constexpr int MINW = sizeof(Real) == 4 ? 0 : CAV_F64_STEP_WAVES;
+    // planes of loads in flight ahead of the computed plane
+    static constexpr int DEPTH = sizeof(Real) == 4 ? 3 : CAV_F64_STEP_DEPTH;
 };
 
 // FIELD = false: the hot wall is the scalar t_hot, known at compile time to
 // need no field loads (the kernel the uniform-wall problem runs).
 template <typename Real, bool NORM, bool FIELD>
-__global__ __launch_bounds__(StepTile<Real>::THREADS) void sweep_kernel(Dims d, Coef cd, SweepGeom g,
+__global__ __launch_bounds__(StepTile<Real>::THREADS, StepTile<Real>::MINW) void sweep_kernel(Dims d, Coef cd, SweepGeom g,
                                                                         CStateT<Real> q, StateT<Real> qn,
                                                                         double* partials)
 {
@@ -43,7 +47,7 @@ __global__ __launch_bounds__(StepTile<Real>::THREADS) void sweep_kernel(Dims d, 
     if constexpr (!FIELD) c.t_hot_field = nullptr;
     const TileBox tb = tile_box<TI, TJ>(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
     StepEpi<Real> epi{qn, Real(0)};
-    sweep_tile<Real, NORM, OwnAll, StepEpi<Real>, 3, TI, TJ>(d, c, tb, OwnAll{}, q, epi, partials, L);
+    sweep_tile<Real, NORM, OwnAll, StepEpi<Real>, StepTile<Real>::DEPTH, TI, TJ>(d, c, tb, OwnAll{}, q, epi, partials, L);
 }
 
 SweepGeom sweep_geom(const Dims& d, int slots, int ti, int tj)
@@ -289,17 +293,35 @@ struct BatchTiles {
     static constexpr int DEPTH = F32 ? 3 : 2;
 };
 
+// The item walk of one block: with at least BATCH_SEGS blocks, block b
+// (on XCD b % 8) takes every (blocks on its XCD)-th item of segment b % 8;
+// with fewer blocks, block b walks whole segments b, b + gridDim.x, ...
+template <typename F>
+__device__ __forceinline__ void for_each_item(const int* __restrict__ segs, F&& body)
+{
+    const int G = gridDim.x, b = blockIdx.x;
+    if (G >= BATCH_SEGS) {
+        const int s = b % BATCH_SEGS, lb = b / BATCH_SEGS;
+        const int nbs = (G - s + BATCH_SEGS - 1) / BATCH_SEGS;      // blocks on segment s
+        for (int it = segs[s] + lb; it < segs[s + 1]; it += nbs) body(it);
+    } else {
+        for (int s = b; s < BATCH_SEGS; s += G)
+            for (int it = segs[s]; it < segs[s + 1]; ++it) body(it);
+    }
+}
+
 template <typename Real, bool NORM>
 __global__ __launch_bounds__(BatchTiles<Real>::THREADS) void batch_kernel(const BatchCav* __restrict__ cavs,
+                                                                          const int* __restrict__ segs,
                                                                           const BatchItem* __restrict__ items,
-                                                                          int nitems, int parity)
+                                                                          int parity)
 {
     using BT = BatchTiles<Real>;
     __shared__ union {
         SweepLds<Real, BT::WTI, BT::WTJ> wide;
         SweepLds<Real, BT::NTI, BT::NTJ> narrow;
     } L;
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    for_each_item(segs, [&](int it) {
         const BatchItem w = items[it];
         const BatchCav& cv = cavs[w.cav];
         const Dims d = cv.d;
@@ -324,22 +346,22 @@ __global__ __launch_bounds__(BatchTiles<Real>::THREADS) void batch_kernel(const 
                 d, c, tb, OwnAll{}, qs, epi, cv.ws + WS_HEAD_DOUBLES, L.wide);
         }
         __syncthreads();                  // LDS is reused by the next item
-    }
+    });
 }
 
 template <typename Real>
-hipError_t launch_batch(const BatchCav* cavs, const BatchItem* items, int nitems, int parity, bool with_norm,
+hipError_t launch_batch(const BatchCav* cavs, const int* segs, const BatchItem* items, int parity, bool with_norm,
                         int nblocks, hipStream_t s)
 {
     dim3 block(SW_TI, BatchTiles<Real>::THREADS / SW_TI), grid(nblocks);
     if (with_norm)
-        batch_kernel<Real, true><<<grid, block, 0, s>>>(cavs, items, nitems, parity);
+        batch_kernel<Real, true><<<grid, block, 0, s>>>(cavs, segs, items, parity);
     else
-        batch_kernel<Real, false><<<grid, block, 0, s>>>(cavs, items, nitems, parity);
+        batch_kernel<Real, false><<<grid, block, 0, s>>>(cavs, segs, items, parity);
     return hipGetLastError();
 }
-template hipError_t launch_batch<double>(const BatchCav*, const BatchItem*, int, int, bool, int, hipStream_t);
-template hipError_t launch_batch<float>(const BatchCav*, const BatchItem*, int, int, bool, int, hipStream_t);
+template hipError_t launch_batch<double>(const BatchCav*, const int*, const BatchItem*, int, bool, int, hipStream_t);
+template hipError_t launch_batch<float>(const BatchCav*, const int*, const BatchItem*, int, bool, int, hipStream_t);
 
 // Residual norms of every member: one block per member, the same
 // fixed-order reduction as the single-cavity finalize.

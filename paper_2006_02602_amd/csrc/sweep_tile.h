@@ -98,14 +98,17 @@ struct OwnAll {
 // are updated (and enter the norm).  Used by the single-cavity sweep, the
 // batched kernel and the interior/exterior split.  The block has TI x TJ =
 // 512 or 256 threads, launched as SW_TI x (TI TJ / SW_TI): thread t = lane +
-// TI * row works on column (i0 + lane, j0 + row); TI >= 16 and TJ >= 8 (the
-// halo roles below need 12 threads per row and 8 rows).
+// TI * row works on column (i0 + lane, j0 + row); TI >= 16 and TJ >= 4 (the
+// halo roles below need 12 threads per row; 4-row tiles give each thread
+// two of the eight u v w T halo rows).
 template <typename Real, bool NORM, typename Own, typename Epi, int DEPTH = 3, int TI = SW_TI, int TJ = SW_TJ>
 __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, const TileBox& tb, const Own& own,
                                            const CStateT<Real>& q, Epi& epi, double* partials,
                                            SweepLds<Real, TI, TJ>& L)
 {
-    static_assert((TI * TJ == 512 || TI * TJ == 256) && TI >= 16 && TJ >= 8, "512- or 256-thread tiles, TI >= 16, TJ >= 8");
+    static_assert((TI * TJ == 512 || TI * TJ == 256) && TI >= 16 && (TJ >= 8 || TJ == 4),
+                  "512- or 256-thread tiles, TI >= 16, TJ = 4 or >= 8");
+    constexpr int UR = TJ >= 8 ? 1 : 2;            // u v w T halo rows per thread
     using Lds = SweepLds<Real, TI, TJ>;
     constexpr int PW = Lds::PW, UW = Lds::UW;
     constexpr int PPL = Lds::PPL, UPL = Lds::UPL;
@@ -135,12 +138,23 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
     const int prow_lds = row < 2 ? row : TJ + row;
     const int prow_j = j0 - 2 + prow_lds;
     const bool ld_prow = has_prow && interior(i, prow_j) && own.column(i, prow_j);
-    // u v w T rows j0-1, j0+TJ: rows 0..7, field 1 + row/2
-    const bool has_urow = row < 8;
-    const int urow_f = FU + (min(row, 7) >> 1);
-    const int urow_lds = (row & 1) ? TJ + 1 : 0;
-    const int urow_j = j0 - 1 + urow_lds;
-    const bool ld_urow = has_urow && interior(i, urow_j) && own.column(i, urow_j);
+    // u v w T rows j0-1, j0+TJ: slot s = 0..7 is field 1 + s/2, side s&1;
+    // this thread's slots are row (and row + 4 in 4-row tiles)
+    bool has_urow[UR], ld_urow[UR];
+    int urow_dst[UR], off_urow[UR];
+    const Real* URg[UR];
+#pragma unroll
+    for (int r = 0; r < UR; ++r) {
+        const int sl = row + 4 * r;
+        has_urow[r] = sl < 8;
+        const int uf = FU + (min(sl, 7) >> 1);
+        const int ul = (sl & 1) ? TJ + 1 : 0;
+        const int uj = j0 - 1 + ul;
+        ld_urow[r] = has_urow[r] && interior(i, uj) && own.column(i, uj);
+        urow_dst[r] = (uf - FU) * UPL + ul * UW + lane + 1;
+        off_urow[r] = cell_off(d, i, uj, 0);
+        URg[r] = q.f[uf];
+    }
     // column halos of this wave's row: lanes 0..3 p (i0-2, i0-1, i0+TI,
     // i0+TI+1), lanes 4..11 u v w T (i0-1, i0+TI)
     const bool has_col = lane < 12;
@@ -159,17 +173,14 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
     }
     const bool ld_col = has_col && interior(col_i, j);
     const int prow_dst = prow_lds * PW + lane + 2;
-    const int urow_dst = (urow_f - FU) * UPL + urow_lds * UW + lane + 1;
     const int off_c = cell_off(d, i, j, 0);
     const int off_prow = cell_off(d, i, prow_j, 0);
-    const int off_urow = cell_off(d, i, urow_j, 0);
     const int off_col = cell_off(d, col_i, j, 0);
     const Real* const Pg = q.f[FP];
     const Real* const Ug = q.f[FU];
     const Real* const Vg = q.f[FV];
     const Real* const Wg = q.f[FW];
     const Real* const Tg = q.f[FT];
-    const Real* const URg = q.f[urow_f];
     const Real* const COLg = q.f[col_f];
     const int Z = d.sz;
 
@@ -180,9 +191,9 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
             return f == FP ? fP[(cj - j0 + 2) * PW + (ci - i0 + 2)]
                            : fU[(f - FU) * UPL + (cj - j0 + 1) * UW + (ci - i0 + 1)];
         };
-        // y walls: column i0 + lane, field `row`
-        if (row < NF && i < d.ni) {
-            const int f = row, reach = f == FP ? 2 : 1;
+        // y walls: column i0 + lane, fields row, row + TJ, ...
+        for (int f = row; f < NF && i < d.ni; f += TJ) {
+            const int reach = f == FP ? 2 : 1;
             if (j0 == 0) {
                 const Real a = cell(f, i, 0), b = cell(f, i, 1);
                 for (int gg = 1; gg <= reach; ++gg) cell(f, i, -gg) = ghost_value(f, gg | (SIDE_OTHER << 2), a, b, c, c.t_hot);
@@ -246,7 +257,9 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
     sU[2 * UPL + lc_u] = w1;
     sU[3 * UPL + lc_u] = t1;
     if (has_prow) sP[prow_dst] = ld_prow ? Pg[off_prow + k0 * Z] : Real(0);
-    if (has_urow) sU[urow_dst] = ld_urow ? URg[off_urow + k0 * Z] : Real(0);
+#pragma unroll
+    for (int r = 0; r < UR; ++r)
+        if (has_urow[r]) sU[urow_dst[r]] = ld_urow[r] ? URg[r][off_urow[r] + k0 * Z] : Real(0);
     if (has_col) (col_f == FP ? sP : sU)[col_lds] = ld_col ? COLg[off_col + k0 * Z] : Real(0);
 
     // Loads run DEPTH planes ahead: what the iteration for plane k needs
@@ -254,7 +267,7 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
     // is issued while plane k-DEPTH is computed; DEPTH register sets rotate
     // (3 for the step kernels; 2 where the epilogue needs the registers).
     struct InFlight {
-        Real p, u, v, w, t, prow, urow, col;
+        Real p, u, v, w, t, prow, urow[UR], col;
     };
     auto issue = [&](InFlight& F, int k) __attribute__((always_inline)) {
         if (active) {
@@ -268,12 +281,14 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
         }
         if (k + 1 < k1) {
             if (ld_prow) F.prow = Pg[off_prow + (k + 1) * Z];
-            if (ld_urow) F.urow = URg[off_urow + (k + 1) * Z];
+#pragma unroll
+            for (int r = 0; r < UR; ++r)
+                if (ld_urow[r]) F.urow[r] = URg[r][off_urow[r] + (k + 1) * Z];
             if (ld_col) F.col = COLg[off_col + (k + 1) * Z];
         }
     };
     static_assert(DEPTH == 2 || DEPTH == 3, "prefetch depth is 2 or 3 planes");
-    InFlight X{0, 0, 0, 0, 0, 0, 0, 0}, Y{0, 0, 0, 0, 0, 0, 0, 0}, Zs{0, 0, 0, 0, 0, 0, 0, 0};
+    InFlight X{}, Y{}, Zs{};
     issue(X, k0);
     if (k0 + 1 < k1) issue(Y, k0 + 1);
     if constexpr (DEPTH == 3)
@@ -299,7 +314,9 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
             nU[2 * UPL + lc_u] = w2;
             nU[3 * UPL + lc_u] = t2;
             if (has_prow) nP[prow_dst] = F.prow;
-            if (has_urow) nU[urow_dst] = F.urow;
+#pragma unroll
+            for (int r = 0; r < UR; ++r)
+                if (has_urow[r]) nU[urow_dst[r]] = F.urow[r];
             if (has_col) (col_f == FP ? nP : nU)[col_lds] = F.col;
         }
         if (k + DEPTH < k1) issue(F, k + DEPTH);
