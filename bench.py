@@ -428,6 +428,8 @@ def main():
     ap.add_argument("--no-oracle", action="store_true",
                     help="skip the FP32 and batch legs' comparisons with the FP64 oracle (about 45 s of host time)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--settle", type=float, default=1.0,
+                    help="seconds of continuous stepping before the warm-up steps (clock ramp-up)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -469,6 +471,17 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    # Clock settle: the GPU's clocks ramp up under sustained load, and a few
+    # milliseconds of work (5 warm-up steps are about 2 ms) leave the sweep
+    # ~7% slower than in steady state.  Step continuously for `settle`
+    # seconds first (reported below), then the W warm-up steps.
+    t0 = time.perf_counter()
+    settle_steps = 0
+    while time.perf_counter() - t0 < args.settle:
+        cav.step(10)
+        torch.cuda.synchronize()
+        settle_steps += 10
+    settle_s = time.perf_counter() - t0
     if W:
         cav.step(W)
     torch.cuda.synchronize()
@@ -572,6 +585,8 @@ def main():
                      "time_source": "HIP events around each sweep launch in this run (same stream)",
                      "counter": counter, "sweep_source_hash": kh},
         "breakdown_us_per_launch": breakdown,
+        "settle": {"seconds": settle_s, "steps": settle_steps,
+                   "why": "untimed continuous steps before the warm-up so that the timed steps run at steady clocks"},
         "ms_per_step_with_events": 1e3 * t_ev / K,
         "ms_per_step_second_pass": 1e3 * t_again / K,
         "residual_norms": norms,
