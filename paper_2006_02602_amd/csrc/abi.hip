@@ -219,6 +219,20 @@ size_t halo_elems(const HaloGeom& h)
     return (size_t)(faces_area * h.wsum);
 }
 
+// Whether the sweep's epilogue packs the exchange: a split along i only
+// (every face is an i face, the noncontiguous kind), every column in at most
+// one face box (subdomain extent along i >= 2 x the largest width), buffer
+// offsets within 32 bits.  Other splits keep the pack kernel: there the
+// epilogue's extra stores cost the sweep more than the i faces' pack costs
+// (2x2x2 at 256^3: sweep +33 us for pack -20 us, unpack +10 us).
+bool xpack_fusable(const HaloGeom& hg)
+{
+    int wmax = 0;
+    for (int f = 0; f < NF; ++f) wmax = std::max(wmax, hg.w[f]);
+    return hg.P[0] > 1 && hg.P[1] == 1 && hg.P[2] == 1 && wmax > 0 && hg.e[0] >= 2 * wmax &&
+           halo_elems(hg) < (size_t)INT32_MAX;
+}
+
 constexpr size_t WS_HEAD = 64;   // 5 final norms, padded
 
 // Sweep blocks resident at once: one per compute unit (the sweep needs
@@ -337,14 +351,15 @@ struct BatchGraph {
 };
 
 int do_halo(const cav_grid* grid, const HaloGeom& hg, void* q, void* buf, bool pack, hipStream_t s,
-            bool timed = true)
+            bool timed = true, int first_axis = 0)
 {
     if (hg.blk_end[2] == 0 || hg.wsum == 0) return CAV_OK;       // nothing to exchange
     const Dims d = dims_of(grid);
     auto launch = [&] {
         return grid->dtype == CAV_F32
-                   ? launch_halo<float>(d, hg, state_of<float>(q, d), static_cast<float*>(buf), pack, s)
-                   : launch_halo<double>(d, hg, state_of<double>(q, d), static_cast<double*>(buf), pack, s);
+                   ? launch_halo<float>(d, hg, state_of<float>(q, d), static_cast<float*>(buf), pack, s, first_axis)
+                   : launch_halo<double>(d, hg, state_of<double>(q, d), static_cast<double*>(buf), pack, s,
+                                         first_axis);
     };
     hipError_t e = timed ? run(pack ? "halo_pack" : "halo_unpack", s, launch) : launch();
     return e == hipSuccess ? CAV_OK : hip_fail(pack ? "halo_pack launch" : "halo_unpack launch", e);
@@ -365,19 +380,24 @@ int step_impl(const cav_grid* grid, const cav_params* prm, const cav_halo* halo,
     const Coef c = coef_of(grid, prm);
     const SweepGeom g = step_geom<Real>(d, device_slots());
     auto go = [&](const char* name, auto&& launch) { return timed ? run(name, stream, launch) : launch(); };
+    // the sweep of step n packs the i faces of step n+1's exchange when the
+    // split allows (xfuse); that step's pack then moves the j and k faces
+    const bool xfuse = halo && xpack_fusable(hg);
     void* cur = q;
     void* nxt = q_tmp;
     hipError_t e;
     for (int n = 0; n < nsteps; ++n) {
         // the wall ghosts are derived inside the sweep; no separate pass
         if (halo) {
-            if ((rc = do_halo(grid, hg, cur, halo_buf, true, stream, timed))) return rc;
+            const int first_axis = xfuse && n > 0 ? 1 : 0;
+            if ((rc = do_halo(grid, hg, cur, halo_buf, true, stream, timed, first_axis))) return rc;
             if ((rc = do_halo(grid, hg, cur, halo_buf, false, stream, timed))) return rc;
         }
         const bool last = n == nsteps - 1 && norms;
-        e = go(last ? "sweep_norm" : "sweep", [&] {
+        const bool xp = xfuse && n < nsteps - 1;
+        e = go(last ? "sweep_norm" : (xp ? "sweep_xpack" : "sweep"), [&] {
             return launch_sweep<Real>(d, c, g, cstate_of<Real>(cur, d), state_of<Real>(nxt, d), partials, last,
-                                      stream);
+                                      stream, xp ? &hg : nullptr, xp ? static_cast<Real*>(halo_buf) : nullptr);
         });
         if (e != hipSuccess) return hip_fail("sweep launch", e);
         void* t = cur;
@@ -645,7 +665,6 @@ int cavity_step_overlap(const cav_grid* grid, const cav_params* prm, const cav_h
     if (!halo) return fail(CAV_EINVAL, "halo is NULL (the split needs the exchange it overlaps)");
     if (!q || !q_tmp || !ws) return fail(CAV_EINVAL, "q, q_tmp and ws must not be NULL");
     if (q == q_tmp) return fail(CAV_EINVAL, "q and q_tmp must be distinct buffers");
-    const Dims d = dims_of(grid);
     const size_t need_ws = ws_bytes_of(grid);
     if (ws_bytes < need_ws) return fail(CAV_ESIZE, "ws_bytes %zu < required %zu", ws_bytes, need_ws);
     HaloGeom hg;

@@ -152,12 +152,14 @@ hipError_t launch_init(const Dims& d, double t_hot, double t_cold, uint64_t seed
                        StateT<Real> q, hipStream_t s);
 template <typename Real>
 hipError_t launch_sweep(const Dims& d, const Coef& c, const SweepGeom& g, CStateT<Real> q, StateT<Real> qn,
-                        double* partials, bool with_norm, hipStream_t s);
+                        double* partials, bool with_norm, hipStream_t s, const HaloGeom* xh = nullptr,
+                        Real* xbuf = nullptr);
 hipError_t launch_norm_finalize(const double* partials, int nblocks, double ncell, double* out,
                                 hipStream_t s);
+// first_axis 1: only the j and k faces (their block ranges)
 template <typename Real>
 hipError_t launch_halo(const Dims& d, const HaloGeom& h, StateT<Real> q, Real* buf, bool pack,
-                       hipStream_t s);
+                       hipStream_t s, int first_axis = 0);
 template <typename Real>
 hipError_t launch_batch(const BatchCav* cavs, const int* segs, const BatchItem* items, int parity, bool with_norm,
                         int nblocks, hipStream_t s);

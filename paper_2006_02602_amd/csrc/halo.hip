@@ -46,10 +46,10 @@ __device__ __forceinline__ void face_of(const HaloGeom& h, int axis, int fidx, i
 }
 
 template <typename Real, bool PACK>
-__global__ __launch_bounds__(HALO_THREADS) void halo_kernel(Dims d, HaloGeom h, StateT<Real> q, Real* buf)
+__global__ __launch_bounds__(HALO_THREADS) void halo_kernel(Dims d, HaloGeom h, StateT<Real> q, Real* buf, int blk0)
 {
     using R2 = typename Pair<Real>::T;
-    int blk = blockIdx.x;
+    int blk = blockIdx.x + blk0;
     const int axis = blk < h.blk_end[0] ? 0 : (blk < h.blk_end[1] ? 1 : 2);
     if (axis > 0) blk -= h.blk_end[axis - 1];
     const int fidx = blk / h.bpf[axis], fblk = blk - fidx * h.bpf[axis];
@@ -179,18 +179,22 @@ __global__ __launch_bounds__(HALO_THREADS) void halo_kernel(Dims d, HaloGeom h, 
     }
 }
 
+// first_axis 1 launches only the j- and k-face block ranges (the i faces
+// were packed by the sweep's epilogue).
 template <typename Real>
-hipError_t launch_halo(const Dims& d, const HaloGeom& h, StateT<Real> q, Real* buf, bool pack, hipStream_t s)
+hipError_t launch_halo(const Dims& d, const HaloGeom& h, StateT<Real> q, Real* buf, bool pack, hipStream_t s,
+                       int first_axis)
 {
-    const int nb = h.blk_end[2];
-    if (nb == 0) return hipSuccess;
+    const int blk0 = first_axis > 0 ? h.blk_end[first_axis - 1] : 0;
+    const int nb = h.blk_end[2] - blk0;
+    if (nb <= 0) return hipSuccess;
     if (pack)
-        halo_kernel<Real, true><<<nb, HALO_THREADS, 0, s>>>(d, h, q, buf);
+        halo_kernel<Real, true><<<nb, HALO_THREADS, 0, s>>>(d, h, q, buf, blk0);
     else
-        halo_kernel<Real, false><<<nb, HALO_THREADS, 0, s>>>(d, h, q, buf);
+        halo_kernel<Real, false><<<nb, HALO_THREADS, 0, s>>>(d, h, q, buf, blk0);
     return hipGetLastError();
 }
-template hipError_t launch_halo<double>(const Dims&, const HaloGeom&, StateT<double>, double*, bool, hipStream_t);
-template hipError_t launch_halo<float>(const Dims&, const HaloGeom&, StateT<float>, float*, bool, hipStream_t);
+template hipError_t launch_halo<double>(const Dims&, const HaloGeom&, StateT<double>, double*, bool, hipStream_t, int);
+template hipError_t launch_halo<float>(const Dims&, const HaloGeom&, StateT<float>, float*, bool, hipStream_t, int);
 
 }  // namespace cav

@@ -34,20 +34,92 @@ struct StepTile {
     static constexpr int DEPTH = sizeof(Real) == 4 ? 3 : CAV_F64_STEP_DEPTH;
 };
 
+// The step's epilogue with the i-face part of the next exchange's pack
+// (Sec. 4.5: the noncontiguous faces that "Optimized V1" packs), for splits
+// along i only: a lane whose column lies within a face width of a cut also
+// stores the new values of its cell at their places in the halo buffer (the
+// layout of halo_pack), so the next step needs no pack kernel.  The values
+// stored are the very ones written to the new state.  Needs every subdomain
+// extent along i >= 2 x the largest width, so that a column lies in at most
+// one face box.
+struct XPackGeom {
+    int ex, pi;          // subdomain extent along i, subdomains along i
+    int nj;              // face rows per plane (the split is along i only)
+    int area;            // face area nj * nk
+    int wsum;
+    int w[NF], wpre[NF];
+};
+
+template <typename Real>
+struct StepXPackEpi : StepEpi<Real> {
+    Real* buf;
+    int dd;          // distance of the column to its cut (< the largest width), or -1: no face
+    int face;        // 0: the -i face of the column's subdomain, 1: its +i face
+    int seg;         // element offset of that face's segment in the buffer
+    XPackGeom x;
+
+    __device__ __forceinline__ void init(const Dims& d, int i)
+    {
+        dd = -1;
+        if (i >= d.ni) return;
+        int wmax = 0;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) wmax = max(wmax, x.w[f]);
+        const int a = i / x.ex;
+        const int lo = i - a * x.ex, hi = x.ex - 1 - lo;
+        if (a > 0 && lo < wmax) { face = 0; dd = lo; }
+        else if (a < x.pi - 1 && hi < wmax) { face = 1; dd = hi; }
+        // segments in subdomain order, -i before +i face (buffer layout):
+        // subdomain 0 has only its +i face, the others both (the last one
+        // only its -i face)
+        seg = (a > 0 ? 2 * a - 1 + face : 0) * x.area * x.wsum;
+    }
+    __device__ __forceinline__ void cell(const CoefR<Real>&, const Star<Real>& s, const Real R[NF], Real dt, int o,
+                                         int, int j, int k, double acc[NF])
+    {
+        const Real nv[NF] = {fma(dt, R[FP], s.p) - this->pc_new, fma(dt, R[FU], s.u), fma(dt, R[FV], s.v),
+                             fma(dt, R[FW], s.w), fma(dt, R[FT], s.t)};
+#pragma unroll
+        for (int f = 0; f < NF; ++f) __builtin_nontemporal_store(nv[f], &this->qn.f[f][o]);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) acc[f] = fma((double)R[f], (double)R[f], acc[f]);
+        if (dd < 0) return;
+        const int row = k * x.nj + j;              // (k, j) index on the face
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const int w = x.w[f];
+            if (dd < w) buf[seg + x.wpre[f] * x.area + row * w + (face ? w - 1 - dd : dd)] = nv[f];
+        }
+    }
+};
+
 // FIELD = false: the hot wall is the scalar t_hot, known at compile time to
-// need no field loads (the kernel the uniform-wall problem runs).
-template <typename Real, bool NORM, bool FIELD>
-__global__ __launch_bounds__(StepTile<Real>::THREADS, StepTile<Real>::MINW) void sweep_kernel(Dims d, Coef cd, SweepGeom g,
-                                                                        CStateT<Real> q, StateT<Real> qn,
-                                                                        double* partials)
+// need no field loads (the kernel the uniform-wall problem runs).  XP: the
+// epilogue also packs the i faces of the new state into xbuf (geometry xh).
+template <typename Real, bool NORM, bool FIELD, bool XP>
+__global__ __launch_bounds__(StepTile<Real>::THREADS, StepTile<Real>::MINW) void sweep_kernel(
+    Dims d, Coef cd, SweepGeom g, CStateT<Real> q, StateT<Real> qn, double* partials, XPackGeom xg, Real* xbuf)
 {
     constexpr int TI = StepTile<Real>::TI, TJ = StepTile<Real>::TJ;
     __shared__ SweepLds<Real, TI, TJ> L;
     CoefR<Real> c = coef_as<Real>(cd);
     if constexpr (!FIELD) c.t_hot_field = nullptr;
     const TileBox tb = tile_box<TI, TJ>(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
-    StepEpi<Real> epi{qn, Real(0)};
-    sweep_tile<Real, NORM, OwnAll, StepEpi<Real>, StepTile<Real>::DEPTH, TI, TJ>(d, c, tb, OwnAll{}, q, epi, partials, L);
+    if constexpr (XP) {
+        StepXPackEpi<Real> epi;
+        epi.qn = qn;
+        epi.pc_new = Real(0);
+        epi.x = xg;
+        epi.buf = xbuf;
+        const int tid = threadIdx.x + SW_TI * threadIdx.y;
+        epi.init(d, tb.i0 + tid % TI);
+        sweep_tile<Real, NORM, OwnAll, StepXPackEpi<Real>, StepTile<Real>::DEPTH, TI, TJ>(d, c, tb, OwnAll{}, q, epi,
+                                                                                         partials, L);
+    } else {
+        StepEpi<Real> epi{qn, Real(0)};
+        sweep_tile<Real, NORM, OwnAll, StepEpi<Real>, StepTile<Real>::DEPTH, TI, TJ>(d, c, tb, OwnAll{}, q, epi,
+                                                                                    partials, L);
+    }
 }
 
 SweepGeom sweep_geom(const Dims& d, int slots, int ti, int tj)
@@ -88,7 +160,7 @@ SweepGeom step_geom(const Dims& d, int cus)
     static int per_cu = 0;
     if (per_cu == 0) {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_kernel<Real, false, false>,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_kernel<Real, false, false, false>,
                                                          StepTile<Real>::THREADS, 0) != hipSuccess ||
             n < 1)
             n = 1;
@@ -99,29 +171,47 @@ SweepGeom step_geom(const Dims& d, int cus)
 template SweepGeom step_geom<double>(const Dims&, int);
 template SweepGeom step_geom<float>(const Dims&, int);
 
-// g comes from step_geom<Real>.
+// g comes from step_geom<Real>.  xh, xbuf: the i-face pack in the epilogue
+// (both NULL: none; never with the norm pass).
 template <typename Real>
 hipError_t launch_sweep(const Dims& d, const Coef& c, const SweepGeom& g, CStateT<Real> q, StateT<Real> qn,
-                        double* partials, bool with_norm, hipStream_t s)
+                        double* partials, bool with_norm, hipStream_t s, const HaloGeom* xh, Real* xbuf)
 {
     dim3 block(SW_TI, StepTile<Real>::THREADS / SW_TI), grid(g.nblocks);
+    XPackGeom xg{};
+    const bool xp = xh && xbuf && !with_norm;
+    if (xp) {
+        xg.ex = xh->e[0];
+        xg.pi = xh->P[0];
+        xg.nj = d.nj;
+        xg.area = (int)xh->area[0];
+        xg.wsum = xh->wsum;
+        for (int f = 0; f < NF; ++f) {
+            xg.w[f] = xh->w[f];
+            xg.wpre[f] = xh->wpre[f];
+        }
+    }
     if (c.t_hot_field) {
         if (with_norm)
-            sweep_kernel<Real, true, true><<<grid, block, 0, s>>>(d, c, g, q, qn, partials);
+            sweep_kernel<Real, true, true, false><<<grid, block, 0, s>>>(d, c, g, q, qn, partials, xg, nullptr);
+        else if (xp)
+            sweep_kernel<Real, false, true, true><<<grid, block, 0, s>>>(d, c, g, q, qn, partials, xg, xbuf);
         else
-            sweep_kernel<Real, false, true><<<grid, block, 0, s>>>(d, c, g, q, qn, partials);
+            sweep_kernel<Real, false, true, false><<<grid, block, 0, s>>>(d, c, g, q, qn, partials, xg, nullptr);
     } else {
         if (with_norm)
-            sweep_kernel<Real, true, false><<<grid, block, 0, s>>>(d, c, g, q, qn, partials);
+            sweep_kernel<Real, true, false, false><<<grid, block, 0, s>>>(d, c, g, q, qn, partials, xg, nullptr);
+        else if (xp)
+            sweep_kernel<Real, false, false, true><<<grid, block, 0, s>>>(d, c, g, q, qn, partials, xg, xbuf);
         else
-            sweep_kernel<Real, false, false><<<grid, block, 0, s>>>(d, c, g, q, qn, partials);
+            sweep_kernel<Real, false, false, false><<<grid, block, 0, s>>>(d, c, g, q, qn, partials, xg, nullptr);
     }
     return hipGetLastError();
 }
 template hipError_t launch_sweep<double>(const Dims&, const Coef&, const SweepGeom&, CStateT<double>,
-                                         StateT<double>, double*, bool, hipStream_t);
+                                         StateT<double>, double*, bool, hipStream_t, const HaloGeom*, double*);
 template hipError_t launch_sweep<float>(const Dims&, const Coef&, const SweepGeom&, CStateT<float>,
-                                        StateT<float>, double*, bool, hipStream_t);
+                                        StateT<float>, double*, bool, hipStream_t, const HaloGeom*, float*);
 
 // ---------------------------------------------------------------------------
 // Interior/exterior split (Sec. 4.7): with a halo exchange in the step, the

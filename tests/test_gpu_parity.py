@@ -143,6 +143,41 @@ def test_pack_unpack_bit_exact(C, n, split, width):
     assert np.array_equal(get_state(C, g, qd), q)
 
 
+@pytest.mark.parametrize("n,split,width,dtype", [
+    ((64, 48, 42), (2, 2, 2), (1, 2, 2, 2, 2), 0),    # k chunks of 5 planes cross the k cut at 21
+    ((64, 48, 40), (4, 2, 1), (2, 1, 1, 1, 1), 0),
+    ((128, 32, 24), (8, 1, 1), (1, 2, 2, 2, 2), 0),   # splits along i: the sweep packs every face
+    ((64, 24, 20), (2, 1, 1), (2, 1, 1, 1, 1), 0),
+    ((128, 16, 12), (8, 1, 1), (1, 2, 2, 2, 2), 1),
+    ((96, 64, 32), (4, 2, 1), (1, 2, 2, 2, 2), 1),
+    ((12, 10, 8), (4, 1, 1), (1, 2, 2, 2, 2), 0),     # i subdomains of 3 cells: no fused i-face pack
+])
+def test_step_exchange_is_the_pack_of_the_new_state(C, n, split, width, dtype):
+    """Within cavity_step, for splits along i only, step m+1's exchange is
+    packed by the sweep of step m as it writes the new state; other splits
+    use the pack kernel.  After two steps the buffer holds step 2's
+    exchange: it must equal halo_pack of the state after one step, and the
+    oracle's pack of it, bit for bit."""
+    import torch
+    say("exchange buffer", n, split, width, dtype)
+    P = O.Problem(*n, Ra=1e5)
+    g, h, prm = C.Grid(*n, dtype=dtype), C.Halo(split, width), C.Params(Ra=1e5)
+    a = C.Cavity(g, prm, h).init(7, 1e-3)
+    q0 = a.q.clone()
+    a.step(1)
+    ref = torch.full_like(a.buf, float("nan"))
+    C.halo_pack(g, h, a.q, ref)
+    torch.cuda.synchronize()
+    q1 = C.state_view(g, a.q).cpu().numpy().astype(np.float64)
+    assert np.array_equal(ref.cpu().numpy().astype(np.float64), O.halo_pack(P, (split, width), q1))
+    b = C.Cavity(g, prm, h)
+    b.q.copy_(q0)
+    b.buf.fill_(float("nan"))
+    b.step(2)
+    torch.cuda.synchronize()
+    assert np.array_equal(b.buf.cpu().numpy(), ref.cpu().numpy())
+
+
 # ---------------------------------------------------------------------------
 def run_both(C, n, Ra, steps, seed, halo=None, noise=1e-3, **kw):
     P, g, prm = problem(C, n, Ra=Ra, **kw)
