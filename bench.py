@@ -262,6 +262,17 @@ def overlap_leg(C, torch, grid, prm, splits, widths, steps):
             row[name + "_ms_per_step"] = 1e3 * (time.perf_counter() - t0) / steps
         C.cavity_timing_read()
         C.cavity_timing_enable(True)
+        cav.step(steps)
+        torch.cuda.synchronize()
+        C.cavity_timing_enable(False)
+        kt = C.cavity_timing_read()
+        # per launch; within a call the sweep of a split along i packs the
+        # next exchange (sweep_xpack), so only the first step runs the pack
+        row["unsplit_kernels"] = {k: {"launches": n, "avg_us": round(1e3 * ms / n, 2)} for k, (n, ms) in sorted(kt.items())
+                                  if k in ("sweep", "sweep_xpack", "sweep_norm", "halo_pack", "halo_unpack")}
+        row["unsplit_exchange_us_per_step"] = round(1e3 * sum(kt[k][1] for k in ("halo_pack", "halo_unpack") if k in kt) / steps, 2)
+        C.cavity_timing_read()
+        C.cavity_timing_enable(True)
         cav.step_overlap(steps, comm_stream=comm)
         torch.cuda.synchronize()
         C.cavity_timing_enable(False)
@@ -428,6 +439,7 @@ def main():
     ap.add_argument("--no-oracle", action="store_true",
                     help="skip the FP32 and batch legs' comparisons with the FP64 oracle (about 45 s of host time)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--halo-reps", type=int, default=10, help="pack/unpack pairs per halo row and mode")
     ap.add_argument("--settle", type=float, default=1.0,
                     help="seconds of continuous stepping before the warm-up steps (clock ramp-up)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -505,8 +517,9 @@ def main():
     t_ev = time.perf_counter() - t0
     C.cavity_timing_enable(False)
     kt = C.cavity_timing_read()
-    sw_n = sum(kt[k][0] for k in ("sweep", "sweep_norm") if k in kt)
-    sw_ms = sum(kt[k][1] for k in ("sweep", "sweep_norm") if k in kt) / sw_n
+    sw_keys = ("sweep", "sweep_xpack", "sweep_norm")
+    sw_n = sum(kt[k][0] for k in sw_keys if k in kt)
+    sw_ms = sum(kt[k][1] for k in sw_keys if k in kt) / sw_n
     ncell = grid.ncell
     achieved = SWEEP_BYTES_PER_CELL * ncell / (sw_ms * 1e-3) / 1e9
     kh = sweep_source_hash()
@@ -528,7 +541,7 @@ def main():
     if not args.no_halo_bench:
         splits = wl.splits
         from paper_2006_02602_amd.configs import CONFIG_WIDTHS, PAPER_WIDTHS
-        halo_res = halo_bench(C, torch, grid, cav, splits, (CONFIG_WIDTHS, PAPER_WIDTHS), reps=10)
+        halo_res = halo_bench(C, torch, grid, cav, splits, (CONFIG_WIDTHS, PAPER_WIDTHS), reps=args.halo_reps)
         for r in halo_res:
             log("bench: halo", r)
 
