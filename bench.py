@@ -524,6 +524,21 @@ def main():
     achieved = SWEEP_BYTES_PER_CELL * ncell / (sw_ms * 1e-3) / 1e9
     kh = sweep_source_hash()
     traffic, counter = counter_rates(kh, 1e3 * sw_ms)
+    # the sweep's memory streams without its work (same tiles, order, chunks
+    # and prefetch depth): the ceiling of its access pattern on this device
+    C.cavity_timing_read()
+    C.cavity_timing_enable(True)
+    for _ in range(K):
+        C.cavity_stream_copy(grid, cav.q, cav.q_tmp)
+    torch.cuda.synchronize()
+    C.cavity_timing_enable(False)
+    n_sc, ms_sc = C.cavity_timing_read()["stream_copy"]
+    sc_us = 1e3 * ms_sc / n_sc
+    ceiling = {"kernel": "stream_copy_kernel", "what": "the sweep's 5 reads + 5 non-temporal writes per interior cell, "
+                                                      "same tiles, block order, k chunks and prefetch depth, no work",
+               "avg_launch_us": sc_us, "GBs": SWEEP_BYTES_PER_CELL * grid.ncell / (sc_us * 1e-6) / 1e9,
+               "frac": SWEEP_BYTES_PER_CELL * grid.ncell / (sc_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+               "sweep_over_ceiling_time": 1e3 * sw_ms / sc_us}
     # the same K steps once more without events: how much of the timed pass
     # is the device settling after the short warm-up
     torch.cuda.synchronize()
@@ -596,7 +611,8 @@ def main():
                      "achieved_is": "algorithmic bytes (80 B per interior cell) / average launch time",
                      "avg_launch_us": 1e3 * sw_ms,
                      "time_source": "HIP events around each sweep launch in this run (same stream)",
-                     "counter": counter, "sweep_source_hash": kh},
+                     "counter": counter, "sweep_source_hash": kh,
+                     "ceiling": ceiling},
         "breakdown_us_per_launch": breakdown,
         "settle": {"seconds": settle_s, "steps": settle_steps,
                    "why": "untimed continuous steps before the warm-up so that the timed steps run at steady clocks"},

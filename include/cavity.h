@@ -363,6 +363,15 @@ int cavity_batch_graph_create(const cav_batch* batch, int32_t nsteps, int32_t nb
 int cavity_batch_graph_launch(const cav_batch* batch, void* graph_exec, hipStream_t stream);
 int cavity_batch_graph_destroy(void* graph_exec);
 
+/* Measurement support: the memory streams of cavity_step's sweep without its
+ * work.  Copies the interior cells of all five fields of q into q_tmp with
+ * the sweep's tiles, block order, k chunks and prefetch depth, each value
+ * read once and written once (non-temporal stores); no halo loads, no LDS,
+ * no arithmetic.  Its rate bounds what the sweep's access pattern can reach
+ * on the device.  q: device, read; q_tmp: device, interior cells written
+ * (ghost cells untouched); both cavity_state_elems(grid) elements. */
+int cavity_stream_copy(const cav_grid* grid, const void* q, void* q_tmp, hipStream_t stream);
+
 /* Thread-local description of the last error returned on this thread. */
 const char* cavity_last_error(void);
 

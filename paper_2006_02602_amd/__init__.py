@@ -215,6 +215,14 @@ def cavity_step_overlap(grid, params, halo, q, q_tmp, ws, halo_buf, nsteps: int,
                                     int(nsteps), s, cs))
 
 
+def cavity_stream_copy(grid, q, q_tmp, stream=None) -> None:
+    """The sweep's memory streams without its work (measurement support):
+    copies the interior cells of q into q_tmp with the sweep's tiling."""
+    qp, _ = _ptr(q)
+    tp, _ = _ptr(q_tmp)
+    check(lib().cavity_stream_copy(ctypes.byref(_grid(grid)), qp, tp, _stream(stream)))
+
+
 def halo_pack(grid, halo, q, buf, stream=None) -> None:
     qp, _ = _ptr(q)
     bp, bb = _ptr(buf)

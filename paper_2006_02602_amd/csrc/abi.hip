@@ -949,6 +949,23 @@ int cavity_batch_graph_destroy(void* graph_exec)
     return e == hipSuccess ? CAV_OK : hip_fail("graph destroy", e);
 }
 
+int cavity_stream_copy(const cav_grid* grid, const void* q, void* q_tmp, hipStream_t stream)
+{
+    int rc;
+    if ((rc = check_grid(grid))) return rc;
+    if (!q || !q_tmp) return fail(CAV_EINVAL, "q and q_tmp must not be NULL");
+    if (q == q_tmp) return fail(CAV_EINVAL, "q and q_tmp must be distinct buffers");
+    const Dims d = dims_of(grid);
+    hipError_t e = run("stream_copy", stream, [&] {
+        return grid->dtype == CAV_F32
+                   ? launch_stream_copy<float>(d, step_geom<float>(d, device_slots()), cstate_of<float>(q, d),
+                                               state_of<float>(q_tmp, d), stream)
+                   : launch_stream_copy<double>(d, step_geom<double>(d, device_slots()), cstate_of<double>(q, d),
+                                                state_of<double>(q_tmp, d), stream);
+    });
+    return e == hipSuccess ? CAV_OK : hip_fail("stream copy launch", e);
+}
+
 const char* cavity_last_error(void) { return g_err; }
 
 int cavity_timing_enable(int32_t on)

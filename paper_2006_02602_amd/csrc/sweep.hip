@@ -122,6 +122,54 @@ __global__ __launch_bounds__(StepTile<Real>::THREADS, StepTile<Real>::MINW) void
     }
 }
 
+// The step sweep's memory streams without its work: the same tiles, block
+// order, k chunks and prefetch depth, and per interior cell the five fields
+// read once and written once (non-temporal) -- no halo loads, no LDS, no
+// arithmetic.  Its rate is the ceiling of the sweep's access pattern on the
+// device it runs on.
+template <typename Real>
+__global__ __launch_bounds__(StepTile<Real>::THREADS) void stream_copy_kernel(Dims d, SweepGeom g, CStateT<Real> q,
+                                                                              StateT<Real> qn)
+{
+    constexpr int TI = StepTile<Real>::TI, TJ = StepTile<Real>::TJ, DEPTH = StepTile<Real>::DEPTH;
+    const TileBox tb = tile_box<TI, TJ>(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
+    const int tid = threadIdx.x + SW_TI * threadIdx.y;
+    const int i = tb.i0 + tid % TI, j = tb.j0 + tid / TI;
+    if (i >= d.ni || j >= d.nj) return;
+    const int o0 = cell_off(d, i, j, 0), Z = d.sz;
+    Real v[DEPTH][NF];
+#pragma unroll
+    for (int s = 0; s < DEPTH; ++s)
+        if (tb.k0 + s < tb.k1)
+#pragma unroll
+            for (int f = 0; f < NF; ++f) v[s][f] = q.f[f][o0 + (tb.k0 + s) * Z];
+    for (int k = tb.k0; k < tb.k1; k += DEPTH) {
+#pragma unroll
+        for (int s = 0; s < DEPTH; ++s) {
+            if (k + s < tb.k1) {
+                const int o = o0 + (k + s) * Z;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) __builtin_nontemporal_store(v[s][f], &qn.f[f][o]);
+                if (k + s + DEPTH < tb.k1)
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) v[s][f] = q.f[f][o + DEPTH * Z];
+            }
+        }
+    }
+}
+
+template <typename Real>
+hipError_t launch_stream_copy(const Dims& d, const SweepGeom& g, CStateT<Real> q, StateT<Real> qn, hipStream_t s)
+{
+    dim3 block(SW_TI, StepTile<Real>::THREADS / SW_TI), grid(g.nblocks);
+    stream_copy_kernel<Real><<<grid, block, 0, s>>>(d, g, q, qn);
+    return hipGetLastError();
+}
+template hipError_t launch_stream_copy<double>(const Dims&, const SweepGeom&, CStateT<double>, StateT<double>,
+                                               hipStream_t);
+template hipError_t launch_stream_copy<float>(const Dims&, const SweepGeom&, CStateT<float>, StateT<float>,
+                                              hipStream_t);
+
 SweepGeom sweep_geom(const Dims& d, int slots, int ti, int tj)
 {
     SweepGeom g;

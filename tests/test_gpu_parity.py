@@ -178,6 +178,25 @@ def test_step_exchange_is_the_pack_of_the_new_state(C, n, split, width, dtype):
     assert np.array_equal(b.buf.cpu().numpy(), ref.cpu().numpy())
 
 
+@pytest.mark.parametrize("n,dtype", [((256, 256, 256), 0), ((67, 37, 21), 0), ((96, 40, 33), 1)])
+def test_stream_copy_moves_the_interior(C, n, dtype):
+    """The sweep-stream copy (measurement support) writes every interior
+    cell of every field into q_tmp and nothing else."""
+    import torch
+    say("stream copy", n, dtype)
+    g = C.Grid(*n, dtype=dtype)
+    td = torch.float32 if dtype else torch.float64
+    q = torch.randn(C.cavity_state_elems(g), dtype=torch.float64, device="cuda").to(td)
+    t = torch.full_like(q, float("nan"))
+    C.cavity_stream_copy(g, q, t)
+    a, b = C.state_view(g, q), C.state_view(g, t)
+    inner = (slice(None), slice(2, -2), slice(2, -2), slice(2, -2))
+    assert torch.equal(b[inner], a[inner])
+    ghost = torch.ones_like(b, dtype=torch.bool)
+    ghost[inner] = False
+    assert bool(torch.isnan(b[ghost]).all())
+
+
 # ---------------------------------------------------------------------------
 def run_both(C, n, Ra, steps, seed, halo=None, noise=1e-3, **kw):
     P, g, prm = problem(C, n, Ra=Ra, **kw)
