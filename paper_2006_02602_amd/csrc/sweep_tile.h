@@ -126,7 +126,6 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
     // columns no owned cell's star reaches are neither loaded nor computed
     const bool active = i < d.ni && j < d.nj && own.column(i, j);
 
-    epi.prepare(d, q, c);
 
     // ---- what this thread loads (fixed for the whole march) ----
     // Only interior cells are loaded.  LDS cells that hold wall ghosts are
@@ -293,6 +292,9 @@ __device__ __forceinline__ void sweep_tile(const Dims& d, const CoefR<Real>& c, 
     if (k0 + 1 < k1) issue(Y, k0 + 1);
     if constexpr (DEPTH == 3)
         if (k0 + 2 < k1) issue(Zs, k0 + 2);
+    // the epilogue's per-block setup (for the step: the centre cell's new
+    // pressure, a star gathered from L2) overlaps the loads in flight
+    epi.prepare(d, q, c);
     __syncthreads();
 
     double acc[NF] = {0.0, 0.0, 0.0, 0.0, 0.0};
