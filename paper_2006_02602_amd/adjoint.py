@@ -30,65 +30,106 @@ def segments(nsteps: int, every: int) -> List[Tuple[int, int]]:
 class NusseltAdjoint:
     """J = Nu(q^N) of the cavity started from q0 with hot-wall temperatures
     theta and Rayleigh number Ra; forward() returns J, backward() the
-    gradient (dJ/dtheta, dJ/dRa, dJ/dq0)."""
+    gradient (dJ/dtheta, dJ/dRa, dJ/dq0).
 
-    def __init__(self, grid: Grid, params: Params, nsteps: int, every: int = 20):
+    All buffers (checkpoints, one segment of states, cotangents, wall field)
+    are allocated once per device and reused, so a backward pass allocates
+    nothing.  With graph=True the backward pass is captured into one HIP
+    graph the first time it runs at a given Ra and replayed afterwards (its
+    launches hold Ra's coefficients and the buffers' addresses, which do not
+    change between calls)."""
+
+    def __init__(self, grid: Grid, params: Params, nsteps: int, every: int = 20, graph: bool = False):
         if grid.dtype != CAV_F64:
             raise ValueError("the adjoint is available for FP64 grids only")
         self.grid, self.nsteps, self.every = grid, int(nsteps), int(every)
         self.base = params
         self.segs = segments(self.nsteps, self.every)
-        self.ckpt = []
+        self.graph = bool(graph)
         self.prm: Optional[Params] = None
+        self._b = None            # persistent buffers
+        self._g = None            # captured backward graph
+        self._g_ra = None         # the Ra it was captured at
 
     def _buffers(self, device):
         import torch
-        n = cavity_state_elems(self.grid)
-        tmp = torch.empty(n, dtype=torch.float64, device=device)
-        ws = torch.zeros(cavity_workspace_bytes(self.grid) // 8, dtype=torch.float64, device=device)
-        return tmp, ws
+        if self._b is not None and self._b["dev"] == device:
+            return self._b
+        g = self.grid
+        n = cavity_state_elems(g)
+        f64 = dict(dtype=torch.float64, device=device)
+        self._b = dict(
+            dev=device,
+            ckpt=torch.zeros((max(len(self.segs), 1), n), **f64),
+            states=torch.zeros((max(self.every - 1, 1), n), **f64),
+            q=torch.zeros(n, **f64), tmp=torch.zeros(n, **f64),
+            ws=torch.zeros(cavity_workspace_bytes(g) // 8, **f64),
+            lam=torch.zeros(n, **f64), dth=torch.zeros(g.nj * g.nk, **f64), dra=torch.zeros(1, **f64),
+            aws=torch.zeros(cavity_adjoint_workspace_bytes(g) // 8, **f64),
+            theta=torch.zeros(g.nj * g.nk, **f64))
+        self._g = None
+        return self._b
 
     def forward(self, theta, Ra: float, q0) -> float:
         """Runs the N steps from q0 (flat state tensor, library layout),
         keeping the checkpoints; returns J."""
-        self.theta = theta.detach().contiguous()
-        self.prm = dataclasses.replace(self.base, Ra=float(Ra), t_hot_field=self.theta)
-        tmp, ws = self._buffers(q0.device)
-        q = q0.detach().clone()
-        self.ckpt = []
-        for _, length in self.segs:
-            self.ckpt.append(q.clone())
-            cavity_step(self.grid, self.prm, None, q, tmp, ws, None, length)
-        self.J = cavity_nusselt(self.grid, self.prm, q, ws)
+        B = self._buffers(q0.device)
+        B["theta"].copy_(theta.detach().reshape(-1))
+        self.prm = dataclasses.replace(self.base, Ra=float(Ra), t_hot_field=B["theta"])
+        q = B["q"]
+        q.copy_(q0.detach())
+        for s, (_, length) in enumerate(self.segs):
+            B["ckpt"][s].copy_(q)
+            cavity_step(self.grid, self.prm, None, q, B["tmp"], B["ws"], None, length)
+        self.J = cavity_nusselt(self.grid, self.prm, q, B["ws"])
         return self.J
+
+    def _reverse(self):
+        """Every launch of the backward pass, on the current stream: seed
+        the cotangent of J, then per segment (last to first) recompute its
+        states from the checkpoint and run its reverse steps."""
+        B, g, prm = self._b, self.grid, self.prm
+        lam, dth, dra = B["lam"], B["dth"], B["dra"]
+        dth.zero_()
+        dra.zero_()
+        cavity_nusselt_adjoint(g, prm, lam, dth)
+        for s in reversed(range(len(self.segs))):
+            length = self.segs[s][1]
+            states = [B["ckpt"][s]]
+            for m in range(1, length):
+                st = B["states"][m - 1]
+                st.copy_(states[-1])
+                cavity_step(g, prm, None, st, B["tmp"], B["ws"], None, 1)
+                states.append(st)
+            for st in reversed(states):
+                cavity_adjoint_step(g, prm, st, lam, lam, B["aws"], dth, dra)
 
     def backward(self):
         """(dJ/dtheta (nj*nk), dJ/dRa (1), dJ/dq0 (flat state, zero ghosts))."""
         import torch
         if self.prm is None:
             raise RuntimeError("forward() must run first")
-        g, prm = self.grid, self.prm
-        dev = self.ckpt[0].device if self.ckpt else self.theta.device
-        n = cavity_state_elems(g)
-        lam = torch.zeros(n, dtype=torch.float64, device=dev)
-        dth = torch.zeros(g.nj * g.nk, dtype=torch.float64, device=dev)
-        dra = torch.zeros(1, dtype=torch.float64, device=dev)
-        aws = torch.empty(cavity_adjoint_workspace_bytes(g) // 8, dtype=torch.float64, device=dev)
-        tmp, ws = self._buffers(dev)
-        cavity_nusselt_adjoint(g, prm, lam, dth)
-        for (_, length), ck in zip(reversed(self.segs), reversed(self.ckpt)):
-            states = [ck]
-            for _ in range(length - 1):
-                s = states[-1].clone()
-                cavity_step(g, prm, None, s, tmp, ws, None, 1)
-                states.append(s)
-            for s in reversed(states):
-                cavity_adjoint_step(g, prm, s, lam, lam, aws, dth, dra)
+        B = self._b
+        if not self.graph:
+            self._reverse()
+        elif self._g is not None and self._g_ra == self.prm.Ra:
+            self._g.replay()
+        else:
+            # first pass at this Ra: run it (the results), then capture it
+            # (capture records the launches without running them)
+            self._g = None
+            self._reverse()
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr):
+                self._reverse()
+            self._g, self._g_ra = gr, self.prm.Ra
+        g = self.grid
+        lam = B["lam"]
         dq0 = torch.zeros_like(lam)
         G = g.ng
         inner = (slice(None), slice(G, G + g.nk), slice(G, G + g.nj), slice(G, G + g.ni))
         state_view(g, dq0)[inner] = state_view(g, lam)[inner]
-        return dth, dra, dq0
+        return B["dth"].clone(), B["dra"].clone(), dq0
 
 
 def _function():

@@ -257,6 +257,40 @@ def test_adjoint_step_out_of_place_equals_in_place(C):
     assert np.isfinite(outs[0][0]).all()
 
 
+def test_graph_replay_equals_eager(C):
+    """The backward pass captured in a HIP graph: every replay returns the
+    eager gradient bit for bit, also after eager work on the same buffers
+    between replays and after a change of Ra (which recaptures)."""
+    import torch
+    from paper_2006_02602_amd.adjoint import NusseltAdjoint
+    say("adjoint graph replay")
+    n, steps, every = (24, 16, 12), 13, 5
+    theta = theta_of(n, 6)
+    q0 = O.init(O.Problem(*n), 7, 1e-3)
+    g = C.Grid(*n)
+    th = torch.from_numpy(theta).cuda()
+    q0d = gpu_state(C, g, q0)
+    for Ra in (1e5, 2e4):
+        ref = gradient(C, n, Ra, theta, q0, steps, every)
+        adj = NusseltAdjoint(g, C.Params(), steps, every, graph=True)
+        for rep in range(3):
+            J = adj.forward(th, Ra, q0d)
+            dth, dra, dq0 = adj.backward()
+            torch.cuda.synchronize()
+            assert J == ref[0]
+            assert np.array_equal(dth.cpu().numpy(), ref[1]), (Ra, rep)
+            assert float(dra.cpu()[0]) == ref[2]
+            assert np.array_equal(interior_np(C, g, dq0), ref[3])
+        # a different Ra on the same object: recaptured, still the eager result
+        ref2 = gradient(C, n, 3 * Ra, theta, q0, steps, every)
+        adj.forward(th, 3 * Ra, q0d)
+        dth2, dra2, _ = adj.backward()
+        adj.forward(th, 3 * Ra, q0d)
+        dth3, dra3, _ = adj.backward()
+        assert np.array_equal(dth2.cpu().numpy(), ref2[1]) and np.array_equal(dth3.cpu().numpy(), ref2[1])
+        assert float(dra2.cpu()[0]) == ref2[2] == float(dra3.cpu()[0])
+
+
 def test_autograd_function(C):
     import torch
     from paper_2006_02602_amd import adjoint
