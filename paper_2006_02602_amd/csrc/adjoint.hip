@@ -414,11 +414,11 @@ __global__ __launch_bounds__(ADJ_THREADS) void nusselt_seed_kernel(Dims d, doubl
 }
 
 // Partials of the record pass: one per block of any k-chunk tiling (the
-// chunking never yields more than nk/4 chunks per tile column), NF each.
+// chunking never yields more than nk/CAV_MIN_KC chunks per tile column), NF each.
 long long record_partials(const Dims& d)
 {
     const long long tiles = (long long)((d.ni + SW_TI - 1) / SW_TI) * ((d.nj + SW_TJ - 1) / SW_TJ);
-    return tiles * std::max(1, d.nk / 4) * NF;
+    return tiles * std::max(1, d.nk / CAV_MIN_KC) * NF;
 }
 
 }  // namespace

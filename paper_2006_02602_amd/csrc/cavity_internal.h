@@ -60,6 +60,11 @@ struct Coef {
 constexpr int SW_TI = 64;     // tile width along i (one wavefront)
 constexpr int SW_TJ = 8;      // tile rows along j (one wavefront each)
 
+// Shortest k chunk the launch geometry considers (planes per block).
+#ifndef CAV_MIN_KC
+#define CAV_MIN_KC 2
+#endif
+
 struct SweepGeom {
     int tiles_i, tiles_j;     // tiles per plane
     int kc;                   // k planes per block

@@ -183,7 +183,7 @@ SweepGeom sweep_geom(const Dims& d, int slots, int ti, int tj)
     const int overhead = 3;
     long long best_cost = -1;
     int best = 1;
-    const int max_nkc = max(1, d.nk / 4);
+    const int max_nkc = max(1, d.nk / CAV_MIN_KC);
     for (int nkc = 1; nkc <= max_nkc; ++nkc) {
         const int kc = (d.nk + nkc - 1) / nkc;
         const long long blocks = (long long)tiles * ((d.nk + kc - 1) / kc);

@@ -144,7 +144,7 @@ def test_pack_unpack_bit_exact(C, n, split, width):
 
 
 @pytest.mark.parametrize("n,split,width,dtype", [
-    ((64, 48, 42), (2, 2, 2), (1, 2, 2, 2, 2), 0),    # k chunks of 5 planes cross the k cut at 21
+    ((64, 48, 42), (2, 2, 2), (1, 2, 2, 2, 2), 0),    # the k cut at 21 falls inside a k chunk
     ((64, 48, 40), (4, 2, 1), (2, 1, 1, 1, 1), 0),
     ((128, 32, 24), (8, 1, 1), (1, 2, 2, 2, 2), 0),   # splits along i: the sweep packs every face
     ((64, 24, 20), (2, 1, 1), (2, 1, 1, 1, 1), 0),
