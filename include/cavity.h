@@ -171,6 +171,16 @@ int cavity_step(const cav_grid* grid, const cav_params* prm, const cav_halo* hal
                 void* halo_buf, size_t halo_bytes, int32_t nsteps,
                 hipStream_t stream);
 
+/* One pseudo-time step out of place (Sec. 2; Sec. 3.1): the state after one
+ * step of cavity_step without a halo, read from q_in and written to q_out
+ * (q_in is left unchanged), as a recomputation from a checkpoint needs it.
+ * q_in, q_out: device, cavity_state_elems(grid) elements each, distinct; only
+ * the interior cells of q_out are written.  ws: device workspace as for
+ * cavity_step (the step's residual norms are left there for
+ * cavity_residual_norm), or NULL to skip the norm pass. */
+int cavity_step_from(const cav_grid* grid, const cav_params* prm, const void* q_in,
+                     void* q_out, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Largest number of sweep blocks whose norm partials cavity_step_noalloc's
  * static scratch holds (5 doubles each: 1.25 MiB per device). */
 #define CAV_NOALLOC_MAX_SWEEP_BLOCKS 32768

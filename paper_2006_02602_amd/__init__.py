@@ -182,6 +182,16 @@ def cavity_step(grid, params, halo, q, q_tmp, ws, halo_buf, nsteps: int, stream=
                             int(nsteps), _stream(stream)))
 
 
+def cavity_step_from(grid, params, q_in, q_out, ws=None, stream=None) -> None:
+    """One step out of place: q_out = step(q_in) (no halo); norms into ws
+    when given."""
+    ip, _ = _ptr(q_in)
+    op, _ = _ptr(q_out)
+    wp, wb = _ptr(ws)
+    check(lib().cavity_step_from(ctypes.byref(_grid(grid)), ctypes.byref(_params(params)), ip, op, wp, wb,
+                                 _stream(stream)))
+
+
 def cavity_step_noalloc(grid, params, halo, q, q_tmp, halo_buf, norms, nsteps: int, stream=None) -> None:
     """cavity_step with its norm partials in the library's static device
     array (no workspace; the call allocates nothing).  norms: a device

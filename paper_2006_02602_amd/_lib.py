@@ -25,7 +25,7 @@ ERROR_NAMES = {CAV_EINVAL: "CAV_EINVAL", CAV_ESIZE: "CAV_ESIZE", CAV_EHIP: "CAV_
 
 # every function include/cavity.h declares
 EXPORTS = ("cavity_layout", "cavity_state_elems", "cavity_workspace_bytes", "halo_buffer_bytes", "cavity_init",
-           "cavity_step", "cavity_step_noalloc", "cavity_step_overlap", "halo_pack", "halo_unpack", "cavity_residual_norm", "cavity_nusselt",
+           "cavity_step", "cavity_step_from", "cavity_step_noalloc", "cavity_step_overlap", "halo_pack", "halo_unpack", "cavity_residual_norm", "cavity_nusselt",
            "cavity_adjoint_workspace_bytes", "cavity_nusselt_adjoint", "cavity_adjoint_step",
            "cavity_batch_table_bytes", "cavity_batch_build", "cavity_batch_step", "cavity_batch_graph_create",
            "cavity_batch_graph_launch", "cavity_batch_graph_destroy",
@@ -100,6 +100,8 @@ def lib():
     L.cavity_init.argtypes = [G, Pp, ctypes.c_uint64, ctypes.c_double, vp, vp]
     L.cavity_step.restype = ctypes.c_int
     L.cavity_step.argtypes = [G, Pp, H, vp, vp, vp, sz, vp, sz, i32, vp]
+    L.cavity_step_from.restype = ctypes.c_int
+    L.cavity_step_from.argtypes = [G, Pp, vp, vp, vp, sz, vp]
     L.cavity_step_noalloc.restype = ctypes.c_int
     L.cavity_step_noalloc.argtypes = [G, Pp, H, vp, vp, vp, sz, vp, i32, vp]
     L.cavity_step_overlap.restype = ctypes.c_int

@@ -15,7 +15,7 @@ import dataclasses
 from typing import List, Optional, Tuple
 
 from . import (CAV_F64, Grid, Params, cavity_adjoint_step, cavity_adjoint_workspace_bytes,
-               cavity_nusselt, cavity_nusselt_adjoint, cavity_state_elems, cavity_step,
+               cavity_nusselt, cavity_nusselt_adjoint, cavity_state_elems, cavity_step, cavity_step_from,
                cavity_workspace_bytes, state_view)
 
 
@@ -98,8 +98,7 @@ class NusseltAdjoint:
             states = [B["ckpt"][s]]
             for m in range(1, length):
                 st = B["states"][m - 1]
-                st.copy_(states[-1])
-                cavity_step(g, prm, None, st, B["tmp"], B["ws"], None, 1)
+                cavity_step_from(g, prm, states[-1], st)
                 states.append(st)
             for st in reversed(states):
                 cavity_adjoint_step(g, prm, st, lam, lam, B["aws"], dth, dra)

@@ -634,6 +634,38 @@ int cavity_step(const cav_grid* grid, const cav_params* prm, const cav_halo* hal
                : step_impl<double>(grid, prm, halo, hg, q, q_tmp, partials, norms, halo_buf, nsteps, stream);
 }
 
+int cavity_step_from(const cav_grid* grid, const cav_params* prm, const void* q_in, void* q_out, void* ws,
+                     size_t ws_bytes, hipStream_t stream)
+{
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_params(prm))) return rc;
+    if (!q_in || !q_out) return fail(CAV_EINVAL, "q_in and q_out must not be NULL");
+    if (q_in == q_out) return fail(CAV_EINVAL, "q_in and q_out must be distinct buffers");
+    if (ws && ws_bytes < ws_bytes_of(grid))
+        return fail(CAV_ESIZE, "ws_bytes %zu < required %zu", ws_bytes, ws_bytes_of(grid));
+    const Dims d = dims_of(grid);
+    const Coef c = coef_of(grid, prm);
+    double* norms = static_cast<double*>(ws);
+    double* partials = ws ? reinterpret_cast<double*>(static_cast<char*>(ws) + WS_HEAD) : nullptr;
+    auto one = [&](auto tag) {
+        using Real = decltype(tag);
+        const SweepGeom g = step_geom<Real>(d, device_slots());
+        hipError_t e = run(ws ? "sweep_norm" : "sweep", stream, [&] {
+            return launch_sweep<Real>(d, c, g, cstate_of<Real>(q_in, d), state_of<Real>(q_out, d), partials,
+                                      ws != nullptr, stream);
+        });
+        if (e != hipSuccess) return hip_fail("sweep launch", e);
+        if (ws) {
+            const double ncell = (double)d.ni * d.nj * d.nk;
+            e = run("norm_finalize", stream,
+                    [&] { return launch_norm_finalize(partials, g.nblocks, ncell, norms, stream); });
+            if (e != hipSuccess) return hip_fail("norm finalize launch", e);
+        }
+        return (int)CAV_OK;
+    };
+    return grid->dtype == CAV_F32 ? one(float{}) : one(double{});
+}
+
 int cavity_step_noalloc(const cav_grid* grid, const cav_params* prm, const cav_halo* halo, void* q, void* q_tmp,
                         void* halo_buf, size_t halo_bytes, double* norms, int32_t nsteps, hipStream_t stream)
 {

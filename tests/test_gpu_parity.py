@@ -178,6 +178,28 @@ def test_step_exchange_is_the_pack_of_the_new_state(C, n, split, width, dtype):
     assert np.array_equal(b.buf.cpu().numpy(), ref.cpu().numpy())
 
 
+@pytest.mark.parametrize("n,dtype", [((67, 37, 21), 0), ((64, 64, 64), 0), ((96, 40, 33), 1)])
+def test_step_from_equals_one_step(C, n, dtype):
+    """cavity_step_from (one step out of place) gives cavity_step's state and
+    norms bit for bit and leaves its input unchanged."""
+    import torch
+    say("step from", n, dtype)
+    g, prm = C.Grid(*n, dtype=dtype), C.Params(Ra=1e5)
+    a = C.Cavity(g, prm).init(11, 1e-3)
+    q_in = a.q.clone()
+    out = torch.full_like(a.q, float("nan"))
+    ws = torch.zeros_like(a.ws)
+    C.cavity_step_from(g, prm, q_in, out, ws)
+    a.step(1)
+    inner = (slice(None), slice(2, -2), slice(2, -2), slice(2, -2))
+    assert torch.equal(C.state_view(g, out)[inner], C.state_view(g, a.q)[inner])
+    assert C.cavity_residual_norm(g, ws) == a.norms()
+    b = C.Cavity(g, prm).init(11, 1e-3)
+    assert torch.equal(q_in, b.q)
+    C.cavity_step_from(g, prm, q_in, out)          # no norm pass
+    assert torch.equal(C.state_view(g, out)[inner], C.state_view(g, a.q)[inner])
+
+
 @pytest.mark.parametrize("n,dtype", [((256, 256, 256), 0), ((67, 37, 21), 0), ((96, 40, 33), 1)])
 def test_stream_copy_moves_the_interior(C, n, dtype):
     """The sweep-stream copy (measurement support) writes every interior
