@@ -470,7 +470,8 @@ int scratch_of_current_device(double** out)
 // layer into the stars (width + 2 for p, width + 1 for u v w T); exterior x
 // and y slabs in k chunks of 16 planes, longer if the norm partials would
 // not fit the workspace.
-int split_geom(const cav_grid* grid, const HaloGeom& hg, const SweepGeom& g, size_t ws_bytes, SplitGeom* out)
+int split_geom(const cav_grid* grid, const HaloGeom& hg, const SweepGeom& gi, const SweepGeom& g, size_t ws_bytes,
+               SplitGeom* out)
 {
     const Dims d = dims_of(grid);
     SplitGeom sg;
@@ -487,7 +488,7 @@ int split_geom(const cav_grid* grid, const HaloGeom& hg, const SweepGeom& g, siz
     }
     const size_t cap = (ws_bytes - WS_HEAD) / (NF * sizeof(double));
     for (sg.kce = std::min(16, d.nk);; sg.kce = std::min(2 * sg.kce, d.nk)) {
-        if ((size_t)g.nblocks + exterior_blocks(d, g, sg) <= cap) break;
+        if ((size_t)gi.nblocks + exterior_blocks(d, g, sg) <= cap) break;
         if (sg.kce == d.nk)
             return fail(CAV_ESIZE, "workspace too small for the norm partials of the split sweep");
     }
@@ -502,9 +503,10 @@ int overlap_impl(const cav_grid* grid, const cav_params* prm, const HaloGeom& hg
     int rc;
     const Dims d = dims_of(grid);
     const Coef c = coef_of(grid, prm);
-    const SweepGeom g = sweep_geom(d, device_slots());
+    const SweepGeom gi = step_geom<Real>(d, device_slots());   // interior: the step sweep's tile
+    const SweepGeom g = sweep_geom(d, device_slots());          // exterior slabs: the 64 x 8 tiling
     SplitGeom sg;
-    if ((rc = split_geom(grid, hg, g, ws_bytes, &sg))) return rc;
+    if ((rc = split_geom(grid, hg, gi, g, ws_bytes, &sg))) return rc;
     const int nb_ext = exterior_blocks(d, g, sg);
     double* wsd = static_cast<double*>(ws);
     double* partials = reinterpret_cast<double*>(static_cast<char*>(ws) + WS_HEAD);
@@ -532,21 +534,21 @@ int overlap_impl(const cav_grid* grid, const cav_params* prm, const HaloGeom& hg
         if ((e = hipEventRecord(exchanged, comm)) != hipSuccess) return done(hip_fail("event record", e));
         // interior meanwhile on `stream`, exterior after the exchange
         e = run(last ? "interior_norm" : "interior", stream, [&] {
-            return launch_split<Real>(d, c, g, sg, false, cstate_of<Real>(cur, d), state_of<Real>(nxt, d), partials,
-                                      last, stream);
+            return launch_split<Real>(d, c, gi, g, sg, false, cstate_of<Real>(cur, d), state_of<Real>(nxt, d),
+                                      partials, last, stream);
         });
         if (e != hipSuccess) return done(hip_fail("interior launch", e));
         if ((e = hipStreamWaitEvent(stream, exchanged, 0)) != hipSuccess) return done(hip_fail("stream wait", e));
         e = run(last ? "exterior_norm" : "exterior", stream, [&] {
-            return launch_split<Real>(d, c, g, sg, true, cstate_of<Real>(cur, d), state_of<Real>(nxt, d), partials,
-                                      last, stream);
+            return launch_split<Real>(d, c, gi, g, sg, true, cstate_of<Real>(cur, d), state_of<Real>(nxt, d),
+                                      partials, last, stream);
         });
         if (e != hipSuccess) return done(hip_fail("exterior launch", e));
         std::swap(cur, nxt);
     }
     const double ncell = (double)d.ni * d.nj * d.nk;
     e = run("norm_finalize", stream,
-            [&] { return launch_norm_finalize(partials, g.nblocks + nb_ext, ncell, wsd, stream); });
+            [&] { return launch_norm_finalize(partials, gi.nblocks + nb_ext, ncell, wsd, stream); });
     if (e != hipSuccess) return done(hip_fail("norm finalize launch", e));
     if (cur != q) {
         const size_t bytes = (size_t)NF * field_elems(d) * sizeof(Real);

@@ -184,8 +184,9 @@ struct SplitGeom {
 };
 int exterior_blocks(const Dims& d, const SweepGeom& g, const SplitGeom& sg);
 template <typename Real>
-hipError_t launch_split(const Dims& d, const Coef& c, const SweepGeom& g, const SplitGeom& sg, bool exterior,
-                        CStateT<Real> q, StateT<Real> qn, double* partials, bool with_norm, hipStream_t s);
+hipError_t launch_split(const Dims& d, const Coef& c, const SweepGeom& gi, const SweepGeom& g, const SplitGeom& sg,
+                        bool exterior, CStateT<Real> q, StateT<Real> qn, double* partials, bool with_norm,
+                        hipStream_t s);
 
 // Discrete adjoint (FP64): workspace size in doubles, one reverse step, and
 // the cotangent of the mean hot-wall Nusselt number (scale = ni/3/(nj nk dT)).

@@ -309,28 +309,33 @@ struct OwnSlab {
     }
 };
 
+// The interior launch runs the step sweep's tile of its type (g from
+// step_geom<Real>).
 template <typename Real, bool NORM, bool FIELD>
-__global__ __launch_bounds__(SW_TI * SW_TJ) void interior_kernel(Dims d, Coef cd, SweepGeom g, SplitGeom sg,
-                                                                 CStateT<Real> q, StateT<Real> qn,
-                                                                 double* partials)
+__global__ __launch_bounds__(StepTile<Real>::THREADS) void interior_kernel(Dims d, Coef cd, SweepGeom g, SplitGeom sg,
+                                                                           CStateT<Real> q, StateT<Real> qn,
+                                                                           double* partials, int)
 {
-    __shared__ SweepLds<Real> L;
+    constexpr int TI = StepTile<Real>::TI, TJ = StepTile<Real>::TJ;
+    __shared__ SweepLds<Real, TI, TJ> L;
     CoefR<Real> c = coef_as<Real>(cd);
     if constexpr (!FIELD) c.t_hot_field = nullptr;
-    const TileBox tb = tile_box(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
+    const TileBox tb = tile_box<TI, TJ>(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
     StepEpi<Real> epi{qn, Real(0)};
-    sweep_tile<Real, NORM>(d, c, tb, OwnInterior{sg}, q, epi, partials, L);
+    sweep_tile<Real, NORM, OwnInterior, StepEpi<Real>, StepTile<Real>::DEPTH, TI, TJ>(d, c, tb, OwnInterior{sg}, q,
+                                                                                     epi, partials, L);
 }
 
 // Exterior work items, block b: first the x slabs (per cut: 16 x 32 tiles,
 // j tiles x k chunks of kce planes), then the y slabs (per cut: i tiles x k
 // chunks), then the z slabs (per cut: i x j tiles, the 2m planes around the
 // cut).
-// Norm partials follow the interior launch's, at pidx = nblocks + b.
+// Norm partials follow the interior launch's, at pidx = pidx0 + b (pidx0:
+// the interior launch's block count).  g: the 64 x 8 tiling (sweep_geom).
 template <typename Real, bool NORM, bool FIELD>
 __global__ __launch_bounds__(SW_TI * SW_TJ) void exterior_kernel(Dims d, Coef cd, SweepGeom g, SplitGeom sg,
                                                                  CStateT<Real> q, StateT<Real> qn,
-                                                                 double* partials)
+                                                                 double* partials, int pidx0)
 {
     __shared__ union {
         SweepLds<Real> yz;                       // 64 x 8 tiles for the y and z slabs
@@ -370,7 +375,7 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void exterior_kernel(Dims d, Coef cd
         tb.k0 = cut - sg.m;
         tb.k1 = cut + sg.m;
     }
-    tb.pidx = g.nblocks + b;
+    tb.pidx = pidx0 + b;
     StepEpi<Real> epi{qn, Real(0)};
     if (axis == 0)          // 2m <= 8 owned columns: a narrow tile wastes fewer lanes
         sweep_tile<Real, NORM, OwnSlab, StepEpi<Real>, 3, XS_TI, XS_TJ>(d, c, tb, OwnSlab{sg, axis, cut}, q, epi,
@@ -386,23 +391,28 @@ int exterior_blocks(const Dims& d, const SweepGeom& g, const SplitGeom& sg)
            (sg.P[2] - 1) * g.tiles_i * g.tiles_j;
 }
 
+// gi: the interior launch's geometry (step_geom<Real>); g: the 64 x 8 tiling
+// the exterior slabs are decoded from (sweep_geom).
 template <typename Real>
-hipError_t launch_split(const Dims& d, const Coef& c, const SweepGeom& g, const SplitGeom& sg, bool exterior,
-                        CStateT<Real> q, StateT<Real> qn, double* partials, bool with_norm, hipStream_t s)
+hipError_t launch_split(const Dims& d, const Coef& c, const SweepGeom& gi, const SweepGeom& g, const SplitGeom& sg,
+                        bool exterior, CStateT<Real> q, StateT<Real> qn, double* partials, bool with_norm,
+                        hipStream_t s)
 {
-    dim3 block(SW_TI, SW_TJ);
-    const int nb = exterior ? exterior_blocks(d, g, sg) : g.nblocks;
+    const dim3 block = exterior ? dim3(SW_TI, SW_TJ) : dim3(SW_TI, StepTile<Real>::THREADS / SW_TI);
+    const SweepGeom& gl = exterior ? g : gi;
+    const int nb = exterior ? exterior_blocks(d, g, sg) : gi.nblocks;
+    const int pidx0 = gi.nblocks;
     if (nb == 0) return hipSuccess;
     const bool fld = c.t_hot_field != nullptr;
-#define SPLIT_LAUNCH(K)                                                                                  \
-    do {                                                                                                 \
-        if (fld) {                                                                                       \
-            if (with_norm) K<Real, true, true><<<nb, block, 0, s>>>(d, c, g, sg, q, qn, partials);        \
-            else K<Real, false, true><<<nb, block, 0, s>>>(d, c, g, sg, q, qn, partials);                 \
-        } else {                                                                                         \
-            if (with_norm) K<Real, true, false><<<nb, block, 0, s>>>(d, c, g, sg, q, qn, partials);       \
-            else K<Real, false, false><<<nb, block, 0, s>>>(d, c, g, sg, q, qn, partials);                \
-        }                                                                                                \
+#define SPLIT_LAUNCH(K)                                                                                       \
+    do {                                                                                                      \
+        if (fld) {                                                                                            \
+            if (with_norm) K<Real, true, true><<<nb, block, 0, s>>>(d, c, gl, sg, q, qn, partials, pidx0);     \
+            else K<Real, false, true><<<nb, block, 0, s>>>(d, c, gl, sg, q, qn, partials, pidx0);              \
+        } else {                                                                                              \
+            if (with_norm) K<Real, true, false><<<nb, block, 0, s>>>(d, c, gl, sg, q, qn, partials, pidx0);    \
+            else K<Real, false, false><<<nb, block, 0, s>>>(d, c, gl, sg, q, qn, partials, pidx0);             \
+        }                                                                                                     \
     } while (0)
     if (exterior)
         SPLIT_LAUNCH(exterior_kernel);
@@ -411,10 +421,12 @@ hipError_t launch_split(const Dims& d, const Coef& c, const SweepGeom& g, const 
 #undef SPLIT_LAUNCH
     return hipGetLastError();
 }
-template hipError_t launch_split<double>(const Dims&, const Coef&, const SweepGeom&, const SplitGeom&, bool,
-                                         CStateT<double>, StateT<double>, double*, bool, hipStream_t);
-template hipError_t launch_split<float>(const Dims&, const Coef&, const SweepGeom&, const SplitGeom&, bool,
-                                        CStateT<float>, StateT<float>, double*, bool, hipStream_t);
+template hipError_t launch_split<double>(const Dims&, const Coef&, const SweepGeom&, const SweepGeom&,
+                                         const SplitGeom&, bool, CStateT<double>, StateT<double>, double*, bool,
+                                         hipStream_t);
+template hipError_t launch_split<float>(const Dims&, const Coef&, const SweepGeom&, const SweepGeom&,
+                                        const SplitGeom&, bool, CStateT<float>, StateT<float>, double*, bool,
+                                        hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Batched form: a persistent grid walks the work list of all members; each
