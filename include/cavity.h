@@ -382,6 +382,12 @@ int cavity_batch_graph_destroy(void* graph_exec);
  * (ghost cells untouched); both cavity_state_elems(grid) elements. */
 int cavity_stream_copy(const cav_grid* grid, const void* q, void* q_tmp, hipStream_t stream);
 
+/* Test support: the FP64 square root and reciprocal the step's residual uses
+ * (the hardware estimates refined to within an ulp), on n arguments.
+ * x: device, n doubles > 0 (read); out: device, 2n doubles, written with
+ * out[2m] = sqrt(x[m]) and out[2m+1] = 1/x[m] as the kernels compute them. */
+int cavity_selftest_math(const double* x, double* out, int32_t n, hipStream_t stream);
+
 /* Thread-local description of the last error returned on this thread. */
 const char* cavity_last_error(void);
 

@@ -233,6 +233,16 @@ def cavity_stream_copy(grid, q, q_tmp, stream=None) -> None:
     check(lib().cavity_stream_copy(ctypes.byref(_grid(grid)), qp, tp, _stream(stream)))
 
 
+def cavity_selftest_math(x, out, stream=None) -> None:
+    """Test support: out[2m], out[2m+1] = the kernels' sqrt(x[m]), 1/x[m]."""
+    xp, xb = _ptr(x)
+    op, ob = _ptr(out)
+    n = xb // 8
+    if ob < 16 * n:
+        raise ValueError("out must hold 2 * len(x) float64 values")
+    check(lib().cavity_selftest_math(xp, op, n, _stream(stream)))
+
+
 def halo_pack(grid, halo, q, buf, stream=None) -> None:
     qp, _ = _ptr(q)
     bp, bb = _ptr(buf)

@@ -29,7 +29,7 @@ EXPORTS = ("cavity_layout", "cavity_state_elems", "cavity_workspace_bytes", "hal
            "cavity_adjoint_workspace_bytes", "cavity_nusselt_adjoint", "cavity_adjoint_step",
            "cavity_batch_table_bytes", "cavity_batch_build", "cavity_batch_step", "cavity_batch_graph_create",
            "cavity_batch_graph_launch", "cavity_batch_graph_destroy",
-           "cavity_stream_copy", "cavity_last_error", "cavity_timing_enable", "cavity_timing_read")
+           "cavity_stream_copy", "cavity_selftest_math", "cavity_last_error", "cavity_timing_enable", "cavity_timing_read")
 
 
 class CavGrid(ctypes.Structure):
@@ -135,6 +135,8 @@ def lib():
     L.cavity_batch_graph_destroy.argtypes = [vp]
     L.cavity_stream_copy.restype = ctypes.c_int
     L.cavity_stream_copy.argtypes = [G, vp, vp, vp]
+    L.cavity_selftest_math.restype = ctypes.c_int
+    L.cavity_selftest_math.argtypes = [vp, vp, i32, vp]
     L.cavity_last_error.restype = ctypes.c_char_p
     L.cavity_last_error.argtypes = []
     L.cavity_timing_enable.restype = ctypes.c_int

@@ -1000,6 +1000,14 @@ int cavity_stream_copy(const cav_grid* grid, const void* q, void* q_tmp, hipStre
     return e == hipSuccess ? CAV_OK : hip_fail("stream copy launch", e);
 }
 
+int cavity_selftest_math(const double* x, double* out, int32_t n, hipStream_t stream)
+{
+    if (n < 0) return fail(CAV_EINVAL, "n = %d must be >= 0", n);
+    if (n > 0 && (!x || !out)) return fail(CAV_EINVAL, "x and out must not be NULL");
+    hipError_t e = launch_math(x, out, n, stream);
+    return e == hipSuccess ? CAV_OK : hip_fail("math launch", e);
+}
+
 const char* cavity_last_error(void) { return g_err; }
 
 int cavity_timing_enable(int32_t on)

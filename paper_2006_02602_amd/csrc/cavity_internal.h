@@ -161,6 +161,7 @@ hipError_t launch_sweep(const Dims& d, const Coef& c, const SweepGeom& g, CState
                         Real* xbuf = nullptr);
 hipError_t launch_norm_finalize(const double* partials, int nblocks, double ncell, double* out,
                                 hipStream_t s);
+hipError_t launch_math(const double* x, double* out, int n, hipStream_t s);
 // g comes from step_geom<Real>
 template <typename Real>
 hipError_t launch_stream_copy(const Dims& d, const SweepGeom& g, CStateT<Real> q, StateT<Real> qn, hipStream_t s);

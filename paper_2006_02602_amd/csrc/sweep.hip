@@ -170,6 +170,23 @@ template hipError_t launch_stream_copy<double>(const Dims&, const SweepGeom&, CS
 template hipError_t launch_stream_copy<float>(const Dims&, const SweepGeom&, CStateT<float>, StateT<float>,
                                               hipStream_t);
 
+// The sweep's square root and reciprocal (stencil.h) on an array: out[2m] =
+// sqrt_pos(x[m]), out[2m+1] = recip_pos(x[m]).
+__global__ __launch_bounds__(256) void math_kernel(const double* __restrict__ x, double* __restrict__ out, int n)
+{
+    const int m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= n) return;
+    out[2 * m] = sqrt_pos(x[m]);
+    out[2 * m + 1] = recip_pos(x[m]);
+}
+
+hipError_t launch_math(const double* x, double* out, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    math_kernel<<<(n + 255) / 256, 256, 0, s>>>(x, out, n);
+    return hipGetLastError();
+}
+
 SweepGeom sweep_geom(const Dims& d, int slots, int ti, int tj)
 {
     SweepGeom g;

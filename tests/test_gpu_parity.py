@@ -178,6 +178,39 @@ def test_step_exchange_is_the_pack_of_the_new_state(C, n, split, width, dtype):
     assert np.array_equal(b.buf.cpu().numpy(), ref.cpu().numpy())
 
 
+def test_sqrt_and_reciprocal_within_an_ulp(C):
+    """The residual's FP64 square root (reciprocal-square-root estimate
+    refined by Goldschmidt's iteration and a residual correction) and
+    reciprocal (estimate refined by two Newton steps) against the correctly
+    rounded IEEE results, directly: log-uniform arguments over 1e-290 ..
+    1e290, the range the residual feeds them (u^2 + 4 beta^2 >= 1, sums of
+    lambda/h up to ~1e5), powers of two and their neighbours."""
+    import torch
+    rng = np.random.default_rng(12)
+    x = np.concatenate([
+        10.0 ** rng.uniform(-290, 290, 200000),
+        rng.uniform(1.0, 16.0, 200000),
+        10.0 ** rng.uniform(-1, 6, 200000),
+        np.ldexp(1.0, np.arange(-960, 961)),
+        np.nextafter(np.ldexp(1.0, np.arange(-960, 961)), 0.0),
+        np.nextafter(np.ldexp(1.0, np.arange(-960, 961)), np.inf),
+        [1.0, 2.0, 3.0, 4.0, 0.25, 1e-300 * 10, 1.7976931348623157e+290],
+    ])
+    xd = torch.from_numpy(x).cuda()
+    out = torch.empty(2 * x.size, dtype=torch.float64, device="cuda")
+    C.cavity_selftest_math(xd, out)
+    got = out.cpu().numpy().reshape(-1, 2)
+
+    def ulps(a, b):
+        return np.abs(a.view(np.int64) - b.view(np.int64))
+
+    ds = ulps(got[:, 0], np.sqrt(x))
+    dr = ulps(got[:, 1], 1.0 / x)
+    say("  sqrt: max %d ulp, exact %.4f; reciprocal: max %d ulp, exact %.4f"
+        % (ds.max(), np.mean(ds == 0), dr.max(), np.mean(dr == 0)))
+    assert ds.max() <= 1 and dr.max() <= 1
+
+
 @pytest.mark.parametrize("n,dtype", [((67, 37, 21), 0), ((64, 64, 64), 0), ((96, 40, 33), 1)])
 def test_step_from_equals_one_step(C, n, dtype):
     """cavity_step_from (one step out of place) gives cavity_step's state and
