@@ -311,6 +311,19 @@ def test_step_parity_full_size_odd(C):
     np.testing.assert_allclose(na, nb, rtol=TOL_F64, atol=0)
 
 
+@pytest.mark.parametrize("split,width", [((8, 1, 1), (1, 2, 2, 2, 2)), ((4, 2, 1), (2, 1, 1, 1, 1))])
+def test_step_parity_full_size_other_splits(C, split, width):
+    """256^3, 20 steps with the 1D and 2D splits of the timed halo rows
+    (8x1x1: the sweep's epilogue packs every exchange after the first;
+    4x2x1: the pack kernel), against the oracle with the same exchange."""
+    say("step 256^3 x20", split, width)
+    P, a, b, na, nb = run_both(C, (256, 256, 256), 1e5, 20, 2, halo=(split, width))
+    e = rel_err(a, b)
+    say("rel err", e)
+    assert max(e) <= TOL_F64, e
+    np.testing.assert_allclose(na, nb, rtol=TOL_F64, atol=0)
+
+
 # ---------------------------------------------------------------------------
 def test_quiescent_rest_exact(C):
     say("quiescent")
