@@ -813,8 +813,9 @@ int cavity_adjoint_step(const cav_grid* grid, const cav_params* prm, const void*
     if (ws_bytes < need) return fail(CAV_ESIZE, "ws_bytes %zu < required %zu", ws_bytes, need);
     const Coef c = coef_of(grid, prm);
     const SweepGeom g = sweep_geom(d, device_slots());
+    const SweepGeom gg = gather_geom(d, device_slots());
     hipError_t e = run("adjoint_step", stream, [&] {
-        return launch_adjoint_step(d, c, g, prm->Ra, cstate_of<double>(q_n, d), cstate_of<double>(lam_in, d),
+        return launch_adjoint_step(d, c, g, gg, prm->Ra, cstate_of<double>(q_n, d), cstate_of<double>(lam_in, d),
                                    state_of<double>(lam_out, d), static_cast<double*>(ws), dj_dthot, dj_dra,
                                    stream);
     });

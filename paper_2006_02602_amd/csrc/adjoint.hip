@@ -35,6 +35,16 @@ namespace {
 
 constexpr int NREC = 11;           // record values per cell
 constexpr int ADJ_THREADS = 256;
+// Gather: rows (wavefronts) per block of the LDS tile kernel, and the
+// shortest k chunk it is used for (shorter chunks take the one-cell-per-
+// thread kernel, whose start-up is a single load per value).
+#ifndef CAV_ADJ_GATHER_TJ
+#define CAV_ADJ_GATHER_TJ 8
+#endif
+constexpr int ADJ_GTJ = CAV_ADJ_GATHER_TJ;
+#ifndef CAV_ADJ_TILE_MIN_KC
+#define CAV_ADJ_TILE_MIN_KC 8
+#endif
 enum { R_XX, R_XY, R_XZ, R_BP, R_UB, R_VB, R_WB, R_AU, R_AV, R_AW, R_AT };
 
 // Reverse of cell_residual for one cell, reduced to its record: given the
@@ -249,6 +259,113 @@ struct Nb {
 };
 
 // ---- 3. gather: lambda*(e) plus every star cotangent landing on e ----
+// The per-cell arithmetic, shared by the two gather kernels (which differ
+// only in where the neighbours' records come from), so both give the same
+// bits.  Accumulation order: lambda* and e's own terms, then the axes x, y,
+// z, each with its -1 and +1 neighbours' stars, the fourth-difference
+// terms of the cells two away, and the transposed wall rules.
+struct GatherAcc {
+    double Lp, Lu, Lv, Lw, Lt;
+};
+
+// lam*: lambda at e (the centre cell's p minus the rescale sum); own: e's
+// record (R_XX .. R_AT order).
+__device__ __forceinline__ GatherAcc gather_init(const CoefR<double>& c, const double lam[NF], bool is_centre, double ps,
+                                                 const double own[NREC])
+{
+    const double ctr = -2.0 * ((c.ix2 + c.iy2) + c.iz2);
+    GatherAcc a;
+    a.Lp = (is_centre ? lam[FP] - ps : lam[FP]) - 6.0 * ((own[R_XX] + own[R_XY]) + own[R_XZ]);
+    a.Lu = lam[FU] + (own[R_UB] + ctr * c.nu * own[R_AU]);
+    a.Lv = lam[FV] + (own[R_VB] + ctr * c.nu * own[R_AV]);
+    a.Lw = lam[FW] + (own[R_WB] + ctr * c.nu * own[R_AW]);
+    a.Lt = lam[FT] + (own[R_AW] + ctr * c.alpha * own[R_AT]);
+    return a;
+}
+
+// Axis ax of cell e at coordinate x of nn: the neighbours lo (x-1) and hi
+// (x+1) where they exist, the dissipation terms Xm2, Xp2 of the cells two
+// away where they exist, and e itself (me) for the wall rules.  dth: the
+// dJ/dTheta slot of e's wall row (x = 0 on the i axis), or NULL.
+__device__ __forceinline__ void gather_axis(GatherAcc& a, const CoefR<double>& c, int ax, int x, int nn,
+                                            const Nb& lo, const Nb& hi, double Xm2, double Xp2, const Nb& me,
+                                            double* dth)
+{
+    const double H = ax == 0 ? c.hx2 : (ax == 1 ? c.hy2 : c.hz2);
+    const double I2 = ax == 0 ? c.ix2 : (ax == 1 ? c.iy2 : c.iz2);
+    const double nu = c.nu, al = c.alpha;
+    // the cotangents cell b's star puts on the cell one step from b in
+    // direction dir (+1: up the axis, slot "+"; -1: slot "-")
+    auto t7 = [&](const Nb& b, int dir, double& tu, double& tv, double& tw, double& tt, double& tp) {
+        const double sg = dir > 0 ? -1.0 : 1.0;
+        tp = sg * ((ax == 0 ? b.au : (ax == 1 ? b.av : b.aw)) * H) + 4.0 * b.X;
+        tu = sg * (b.s * b.au + (ax == 0 ? H * b.Bp : 0.0)) + I2 * nu * b.au;
+        tv = sg * (b.s * b.av + (ax == 1 ? H * b.Bp : 0.0)) + I2 * nu * b.av;
+        tw = sg * (b.s * b.aw + (ax == 2 ? H * b.Bp : 0.0)) + I2 * nu * b.aw;
+        tt = sg * (b.s * b.at) + I2 * al * b.at;
+    };
+    double tu, tv, tw, tt, tp;
+    if (x > 0) {                      // the cell below reaches up to e
+        t7(lo, +1, tu, tv, tw, tt, tp);
+        a.Lp += tp; a.Lu += tu; a.Lv += tv; a.Lw += tw; a.Lt += tt;
+    }
+    if (x < nn - 1) {                 // the cell above reaches down to e
+        t7(hi, -1, tu, tv, tw, tt, tp);
+        a.Lp += tp; a.Lu += tu; a.Lv += tv; a.Lw += tw; a.Lt += tt;
+    }
+    if (x >= 2) a.Lp -= Xm2;
+    if (x < nn - 2) a.Lp -= Xp2;
+
+    // walls: ghosts g1, g2 beyond a wall carry the cotangents of the
+    // stars that read them; the wall rules move them onto m0 (next to
+    // the wall) and m1:  p: m0 += 2 g1 + 3 g2, m1 -= g1 + 2 g2;
+    // u v w: m0 -= g1;  T: m0 -= g1 on x walls (and Theta += 2 g1 at
+    // x = 0), m0 += g1 on the others.
+    if (x <= 1 || x >= nn - 2) {
+        for (int side = 0; side < 2; ++side) {
+            const int dir = side ? +1 : -1;          // from m0 towards the wall
+            const int m0 = side ? nn - 1 : 0, m1 = side ? nn - 2 : 1;
+            if (x != m0 && x != m1) continue;
+            const Nb& B0 = x == m0 ? me : (side ? hi : lo);          // m0 seen from e
+            const double X1 = x == m1 ? me.X : (side ? lo.X : hi.X);  // m1's X
+            // g1 collects m0's one-step and m1's two-step reach past the
+            // wall, g2 m0's two-step reach
+            t7(B0, dir, tu, tv, tw, tt, tp);
+            const double g1p = tp - X1, g2p = -B0.X;
+            if (x == m0) {
+                a.Lp += 2.0 * g1p + 3.0 * g2p;
+                a.Lu -= tu;
+                a.Lv -= tv;
+                a.Lw -= tw;
+                if (ax == 0) {
+                    a.Lt -= tt;
+                    if (side == 0 && dth) *dth += 2.0 * tt;
+                } else {
+                    a.Lt += tt;
+                }
+            }
+            if (x == m1) a.Lp -= g1p + 2.0 * g2p;
+        }
+    }
+}
+
+// NT: non-temporal stores (the output is not read again by this pass)
+template <bool NT = false>
+__device__ __forceinline__ void gather_store(const GatherAcc& a, StateT<double>& out, int o)
+{
+    const double v[NF] = {a.Lp, a.Lu, a.Lv, a.Lw, a.Lt};
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        if (NT) __builtin_nontemporal_store(v[f], &out.f[f][o]);
+        else out.f[f][o] = v[f];
+    }
+}
+
+// One cell per thread.  Blocks go to the 8 XCDs round-robin; XCD x walks
+// the rows j of its slab [j0, j0 + w) plane after plane, so that the
+// records a cell reads from its y neighbours (adjacent rows) are in that
+// XCD's L2.  (Its z neighbours' records, a slab-plane away, mostly are not:
+// the blocks in flight on an XCD span more than its L2 holds.)
 __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coef cd, CStateT<double> q,
                                                                      CStateT<double> lam,
                                                                      const double* __restrict__ psum,
@@ -257,10 +374,6 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
 {
     const CoefR<double> c = coef_as<double>(cd);
     const long long n = (long long)d.ni * d.nj * d.nk;
-    // Blocks go to the 8 XCDs round-robin; XCD x walks the rows j of its
-    // slab [j0, j0 + w) plane after plane, so that the records a cell reads
-    // from its y neighbours (adjacent rows) and z neighbours (the same rows
-    // one plane away, w rows earlier) are in that XCD's L2.
     const int x = blockIdx.x & 7;
     const int j0 = (int)((long long)x * d.nj / 8);
     const int w = (int)((long long)(x + 1) * d.nj / 8) - j0;
@@ -272,20 +385,14 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
     const long long idx = i + (long long)d.ni * (j + (long long)d.nj * k);
     const int o = cell_off(d, i, j, k);
     auto R = [&](int v, long long m) { return rec[(size_t)v * n + m]; };
-    const double ctr = -2.0 * ((c.ix2 + c.iy2) + c.iz2);
-    const double nu = c.nu, al = c.alpha;
 
-    // own record, and lambda* (the identity part of q + dt R)
-    const double ps = psum[0];
-    const bool is_centre = o == centre_off(d);
-    const double Xe[3] = {R(R_XX, idx), R(R_XY, idx), R(R_XZ, idx)};
-    const double Bpe = R(R_BP, idx);
-    const double au = R(R_AU, idx), av = R(R_AV, idx), aw = R(R_AW, idx), at = R(R_AT, idx);
-    double Lp = (is_centre ? lam.f[FP][o] - ps : lam.f[FP][o]) - 6.0 * ((Xe[0] + Xe[1]) + Xe[2]);
-    double Lu = lam.f[FU][o] + (R(R_UB, idx) + ctr * nu * au);
-    double Lv = lam.f[FV][o] + (R(R_VB, idx) + ctr * nu * av);
-    double Lw = lam.f[FW][o] + (R(R_WB, idx) + ctr * nu * aw);
-    double Lt = lam.f[FT][o] + (aw + ctr * al * at);
+    double own[NREC];
+#pragma unroll
+    for (int v = 0; v < NREC; ++v) own[v] = R(v, idx);
+    double lm[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) lm[f] = lam.f[f][o];
+    GatherAcc a = gather_init(c, lm, o == centre_off(d), psum[0], own);
 
     // The x neighbours are the cells of the adjacent lanes (a wavefront holds
     // consecutive cells, i fastest): their record values and u arrive by
@@ -293,7 +400,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
     // lane moves before any branch; a lane whose neighbour is no cell of
     // this launch (it returned above) never uses the moved value.
     const int wl = threadIdx.x & 63;
-    const double sh_in[7] = {au, av, aw, at, Xe[0], Bpe, q.f[FU][o]};
+    const double sh_in[7] = {own[R_AU], own[R_AV], own[R_AW], own[R_AT], own[R_XX], own[R_BP], q.f[FU][o]};
     double sh_lo[7], sh_hi[7];
 #pragma unroll
     for (int v = 0; v < 7; ++v) {
@@ -304,12 +411,10 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
     const int N[3] = {d.ni, d.nj, d.nk};
     const long long dstride[3] = {1, d.ni, (long long)d.ni * d.nj};
     const int pstride[3] = {1, d.sy, d.sz};
-    const double h2[3] = {c.hx2, c.hy2, c.hz2};
-    const double i2[3] = {c.ix2, c.iy2, c.iz2};
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        const int x = pos[ax], nn = N[ax];
-        const double H = h2[ax], I2 = i2[ax];
+        const int xx = pos[ax], nn = N[ax];
+        const double H = ax == 0 ? c.hx2 : (ax == 1 ? c.hy2 : c.hz2);
         const double* V = q.f[FU + ax];
         auto nb = [&](int sgn) {
             const long long m = idx + sgn * dstride[ax];
@@ -329,69 +434,212 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
             b.s = V[o + sgn * pstride[ax]] * H;
             return b;
         };
-        // the cotangents cell b's star puts on the cell one step from b in
-        // direction dir (+1: up the axis, slot "+"; -1: slot "-")
-        auto t7 = [&](const Nb& b, int dir, double& tu, double& tv, double& tw, double& tt, double& tp) {
-            const double sg = dir > 0 ? -1.0 : 1.0;
-            tp = sg * ((ax == 0 ? b.au : (ax == 1 ? b.av : b.aw)) * H) + 4.0 * b.X;
-            tu = sg * (b.s * b.au + (ax == 0 ? H * b.Bp : 0.0)) + I2 * nu * b.au;
-            tv = sg * (b.s * b.av + (ax == 1 ? H * b.Bp : 0.0)) + I2 * nu * b.av;
-            tw = sg * (b.s * b.aw + (ax == 2 ? H * b.Bp : 0.0)) + I2 * nu * b.aw;
-            tt = sg * (b.s * b.at) + I2 * al * b.at;
-        };
         Nb lo{0, 0, 0, 0, 0, 0, 0}, hi{0, 0, 0, 0, 0, 0, 0};
-        double tu, tv, tw, tt, tp;
-        if (x > 0) {                      // the cell below reaches up to e
-            lo = nb(-1);
-            t7(lo, +1, tu, tv, tw, tt, tp);
-            Lp += tp; Lu += tu; Lv += tv; Lw += tw; Lt += tt;
-        }
-        if (x < nn - 1) {                 // the cell above reaches down to e
-            hi = nb(+1);
-            t7(hi, -1, tu, tv, tw, tt, tp);
-            Lp += tp; Lu += tu; Lv += tv; Lw += tw; Lt += tt;
-        }
-        if (x >= 2) Lp -= R(R_XX + ax, idx - 2 * dstride[ax]);
-        if (x < nn - 2) Lp -= R(R_XX + ax, idx + 2 * dstride[ax]);
+        if (xx > 0) lo = nb(-1);
+        if (xx < nn - 1) hi = nb(+1);
+        const double Xm2 = xx >= 2 ? R(R_XX + ax, idx - 2 * dstride[ax]) : 0.0;
+        const double Xp2 = xx < nn - 2 ? R(R_XX + ax, idx + 2 * dstride[ax]) : 0.0;
+        const Nb me{own[R_AU], own[R_AV], own[R_AW], own[R_AT], own[R_XX + ax], own[R_BP], V[o] * H};
+        gather_axis(a, c, ax, xx, nn, lo, hi, Xm2, Xp2, me,
+                    (ax == 0 && dthot) ? &dthot[j + (long long)d.nj * k] : nullptr);
+    }
+    gather_store(a, out, o);
+}
 
-        // walls: ghosts g1, g2 beyond a wall carry the cotangents of the
-        // stars that read them; the wall rules move them onto m0 (next to
-        // the wall) and m1:  p: m0 += 2 g1 + 3 g2, m1 -= g1 + 2 g2;
-        // u v w: m0 -= g1;  T: m0 -= g1 on x walls (and Theta += 2 g1 at
-        // x = 0), m0 += g1 on the others.
-        if (x <= 1 || x >= nn - 2) {
-            const Nb me{au, av, aw, at, Xe[ax], Bpe, V[o] * H};
-            for (int side = 0; side < 2; ++side) {
-                const int dir = side ? +1 : -1;          // from m0 towards the wall
-                const int m0 = side ? nn - 1 : 0, m1 = side ? nn - 2 : 1;
-                if (x != m0 && x != m1) continue;
-                const Nb& B0 = x == m0 ? me : (side ? hi : lo);          // m0 seen from e
-                const double X1 = x == m1 ? Xe[ax] : (side ? lo.X : hi.X);   // m1's X
-                // g1 collects m0's one-step and m1's two-step reach past the
-                // wall, g2 m0's two-step reach
-                t7(B0, dir, tu, tv, tw, tt, tp);
-                const double g1p = tp - X1, g2p = -B0.X;
-                if (x == m0) {
-                    Lp += 2.0 * g1p + 3.0 * g2p;
-                    Lu -= tu;
-                    Lv -= tv;
-                    Lw -= tw;
-                    if (ax == 0) {
-                        Lt -= tt;
-                        if (side == 0 && dthot) dthot[j + (long long)d.nj * k] += 2.0 * tt;
-                    } else {
-                        Lt += tt;
-                    }
-                }
-                if (x == m1) Lp -= g1p + 2.0 * g2p;
+// One cell's record and velocity, as the k queue of the tile kernel holds it.
+struct Column {
+    double r[NREC];                    // the cell's record
+    double u, v, w;                    // its velocity (for the neighbours' advection terms)
+};
+
+// The gather as a k-marching LDS tile: a block of 64 x TJ threads marches
+// its (i, j) columns through a k chunk.  Each plane, every thread puts the
+// nine values its in-plane neighbours need (a_u a_v a_w a_T, Bp, the x and
+// y dissipation terms, u, v) into the plane's LDS buffer, the block's
+// threads together add the tile's halo (two rows above and below, two
+// columns left and right, loaded one plane ahead into registers), and after
+// one barrier every cell reads its x and y neighbours from LDS; its z
+// neighbours (one and two planes away) are a register queue that loads each
+// plane once, two planes ahead.  So every record value is read from memory
+// once per tile, plus the halo.  Two LDS buffers alternate between planes:
+// the barrier of plane k+1 orders its writes after every read of plane
+// k-1's buffer.  Every thread runs every plane (no early exit), so the
+// barriers are uniform.
+enum { L_AU, L_AV, L_AW, L_AT, L_BP, L_XX, L_XY, L_U, L_V, NLV };
+
+template <int TJ>
+struct GatherTile {
+    static constexpr int THREADS = 64 * TJ;
+    static constexpr int COLS = 68, ROWS = TJ + 4;            // two halo columns / rows on each side
+    static constexpr int BUF = NLV * ROWS * COLS;             // doubles per plane buffer
+    // halo values per plane: rows -1 and TJ (7 values), rows -2 and TJ+1
+    // (the y dissipation term), columns -1 and 64 (7 values), columns -2
+    // and 65 (the x dissipation term)
+    static constexpr int NH = 2 * 7 * 64 + 2 * 64 + 2 * 7 * TJ + 2 * TJ;
+    static constexpr int SLOTS = (NH + THREADS - 1) / THREADS;
+    __device__ static int at(int v, int row, int col) { return (v * ROWS + row + 2) * COLS + col + 2; }
+};
+
+template <int TJ>
+__global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Coef cd, SweepGeom g,
+                                                                      CStateT<double> q, CStateT<double> lam,
+                                                                      const double* __restrict__ psum,
+                                                                      const double* __restrict__ rec,
+                                                                      StateT<double> out,
+                                                                      double* __restrict__ dthot)
+{
+    using T = GatherTile<TJ>;
+    __shared__ double L[2 * T::BUF];
+    const CoefR<double> c = coef_as<double>(cd);
+    const TileBox tb = tile_box<64, TJ>(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
+    const int lane = threadIdx.x, row = threadIdx.y, tid = lane + 64 * row;
+    const int i = tb.i0 + lane, j = tb.j0 + row;
+    // threads past the grid load a real cell (clamped), take part in every
+    // barrier, and store nothing; no cell of the grid reads their slots
+    const bool active = i < d.ni && j < d.nj;
+    const int ic = min(i, d.ni - 1), jc = min(j, d.nj - 1);
+    const long long n = (long long)d.ni * d.nj * d.nk;
+    const long long plane = (long long)d.ni * d.nj;
+    const long long col = ic + (long long)d.ni * jc;
+    const int ocol = cell_off(d, ic, jc, 0);
+    const int Z = d.sz;
+    const double ps = psum[0];
+    const int centre = centre_off(d);
+
+    // this thread's halo slots: source at k = 0, its stride per plane, and
+    // the LDS slot (-1: outside the grid, nothing to load)
+    const double* hsrc[T::SLOTS];
+    long long hstr[T::SLOTS];
+    int hdst[T::SLOTS];
+#pragma unroll
+    for (int s = 0; s < T::SLOTS; ++s) {
+        int h = tid + s * T::THREADS;
+        int v = -1, hr = 0, hc = 0;
+        if (h < 2 * 7 * 64) {                       // rows -1 and TJ
+            const int side = h / (7 * 64), r = h % (7 * 64);
+            const int vv[7] = {L_AU, L_AV, L_AW, L_AT, L_BP, L_XY, L_V};
+            v = vv[r / 64]; hc = r % 64; hr = side ? TJ : -1;
+        } else if ((h -= 2 * 7 * 64) < 2 * 64) {    // rows -2 and TJ+1
+            v = L_XY; hc = h % 64; hr = h / 64 ? TJ + 1 : -2;
+        } else if ((h -= 2 * 64) < 2 * 7 * TJ) {    // columns -1 and 64
+            const int side = h / (7 * TJ), r = h % (7 * TJ);
+            const int vv[7] = {L_AU, L_AV, L_AW, L_AT, L_BP, L_XX, L_U};
+            v = vv[r / TJ]; hr = r % TJ; hc = side ? 64 : -1;
+        } else if ((h -= 2 * 7 * TJ) < 2 * TJ) {    // columns -2 and 65
+            v = L_XX; hr = h % TJ; hc = h / TJ ? 65 : -2;
+        }
+        const int hi_ = tb.i0 + hc, hj = tb.j0 + hr;
+        hsrc[s] = nullptr;
+        hstr[s] = 0;
+        hdst[s] = -1;
+        if (v >= 0 && hi_ >= 0 && hi_ < d.ni && hj >= 0 && hj < d.nj) {
+            const long long m = hi_ + (long long)d.ni * hj;
+            const int rv[L_U] = {R_AU, R_AV, R_AW, R_AT, R_BP, R_XX, R_XY};
+            if (v < L_U) {
+                hsrc[s] = rec + (size_t)rv[v] * n + m;
+                hstr[s] = plane;
+            } else {
+                hsrc[s] = q.f[v == L_U ? FU : FV] + cell_off(d, hi_, hj, 0);
+                hstr[s] = Z;
             }
+            hdst[s] = T::at(v, hr, hc);
         }
     }
-    out.f[FP][o] = Lp;
-    out.f[FU][o] = Lu;
-    out.f[FV][o] = Lv;
-    out.f[FW][o] = Lw;
-    out.f[FT][o] = Lt;
+    double hv[T::SLOTS];
+    auto load_halo = [&](int k) {
+#pragma unroll
+        for (int s = 0; s < T::SLOTS; ++s)
+            if (hdst[s] >= 0) hv[s] = hsrc[s][k * hstr[s]];
+    };
+
+    auto R = [&](int v, long long m) { return rec[(size_t)v * n + m]; };
+    auto load = [&](int k, Column& C) {
+        const long long m = col + k * plane;
+#pragma unroll
+        for (int v = 0; v < NREC; ++v) C.r[v] = R(v, m);
+        C.u = q.f[FU][ocol + k * Z];
+        C.v = q.f[FV][ocol + k * Z];
+        C.w = q.f[FW][ocol + k * Z];
+    };
+    const int k0 = tb.k0, k1 = tb.k1, nk = d.nk;
+    const double Hx = c.hx2, Hy = c.hy2, Hz = c.hz2;
+    Column cur, nxt, nn2;
+    Nb prv{0, 0, 0, 0, 0, 0, 0};
+    double xm2 = 0.0;
+    if (k0 >= 2) xm2 = R(R_XZ, col + (k0 - 2) * plane);
+    if (k0 >= 1) {
+        const long long m = col + (k0 - 1) * plane;
+        prv = Nb{R(R_AU, m), R(R_AV, m), R(R_AW, m), R(R_AT, m), R(R_XZ, m), R(R_BP, m),
+                 q.f[FW][ocol + (k0 - 1) * Z] * Hz};
+    }
+    load(k0, cur);
+    load_halo(k0);
+    if (k0 + 1 < nk) load(k0 + 1, nxt);
+    if (k0 + 2 < nk) load(k0 + 2, nn2);
+
+    for (int k = k0; k < k1; ++k) {
+        double* B = L + ((k - k0) & 1) * T::BUF;
+        {
+            const double own[NLV] = {cur.r[R_AU], cur.r[R_AV], cur.r[R_AW], cur.r[R_AT], cur.r[R_BP],
+                                     cur.r[R_XX], cur.r[R_XY], cur.u, cur.v};
+#pragma unroll
+            for (int v = 0; v < NLV; ++v) B[T::at(v, row, lane)] = own[v];
+        }
+#pragma unroll
+        for (int s = 0; s < T::SLOTS; ++s)
+            if (hdst[s] >= 0) B[hdst[s]] = hv[s];
+        if (k + 1 < k1) load_halo(k + 1);
+        __syncthreads();
+
+        const int o = ocol + k * Z;
+        double lm[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) lm[f] = lam.f[f][o];
+        GatherAcc a = gather_init(c, lm, o == centre, ps, cur.r);
+        auto nbx = [&](int dc) {
+            return Nb{B[T::at(L_AU, row, lane + dc)], B[T::at(L_AV, row, lane + dc)], B[T::at(L_AW, row, lane + dc)],
+                      B[T::at(L_AT, row, lane + dc)], B[T::at(L_XX, row, lane + dc)], B[T::at(L_BP, row, lane + dc)],
+                      B[T::at(L_U, row, lane + dc)] * Hx};
+        };
+        auto nby = [&](int dr) {
+            return Nb{B[T::at(L_AU, row + dr, lane)], B[T::at(L_AV, row + dr, lane)], B[T::at(L_AW, row + dr, lane)],
+                      B[T::at(L_AT, row + dr, lane)], B[T::at(L_XY, row + dr, lane)], B[T::at(L_BP, row + dr, lane)],
+                      B[T::at(L_V, row + dr, lane)] * Hy};
+        };
+        {
+            const Nb lo = i > 0 ? nbx(-1) : Nb{0, 0, 0, 0, 0, 0, 0};
+            const Nb hi = i < d.ni - 1 ? nbx(+1) : Nb{0, 0, 0, 0, 0, 0, 0};
+            const double Xm2 = i >= 2 ? B[T::at(L_XX, row, lane - 2)] : 0.0;
+            const double Xp2 = i < d.ni - 2 ? B[T::at(L_XX, row, lane + 2)] : 0.0;
+            const Nb me{cur.r[R_AU], cur.r[R_AV], cur.r[R_AW], cur.r[R_AT], cur.r[R_XX], cur.r[R_BP], cur.u * Hx};
+            gather_axis(a, c, 0, i, d.ni, lo, hi, Xm2, Xp2, me,
+                        (dthot && active) ? &dthot[j + (long long)d.nj * k] : nullptr);
+        }
+        {
+            const Nb lo = j > 0 ? nby(-1) : Nb{0, 0, 0, 0, 0, 0, 0};
+            const Nb hi = j < d.nj - 1 ? nby(+1) : Nb{0, 0, 0, 0, 0, 0, 0};
+            const double Xm2 = j >= 2 ? B[T::at(L_XY, row - 2, lane)] : 0.0;
+            const double Xp2 = j < d.nj - 2 ? B[T::at(L_XY, row + 2, lane)] : 0.0;
+            const Nb me{cur.r[R_AU], cur.r[R_AV], cur.r[R_AW], cur.r[R_AT], cur.r[R_XY], cur.r[R_BP], cur.v * Hy};
+            gather_axis(a, c, 1, j, d.nj, lo, hi, Xm2, Xp2, me, nullptr);
+        }
+        {
+            const Nb hi = k < nk - 1 ? Nb{nxt.r[R_AU], nxt.r[R_AV], nxt.r[R_AW], nxt.r[R_AT], nxt.r[R_XZ],
+                                          nxt.r[R_BP], nxt.w * Hz}
+                                     : Nb{0, 0, 0, 0, 0, 0, 0};
+            const double Xp2 = k < nk - 2 ? nn2.r[R_XZ] : 0.0;
+            const Nb me{cur.r[R_AU], cur.r[R_AV], cur.r[R_AW], cur.r[R_AT], cur.r[R_XZ], cur.r[R_BP], cur.w * Hz};
+            gather_axis(a, c, 2, k, nk, k > 0 ? prv : Nb{0, 0, 0, 0, 0, 0, 0}, hi, k >= 2 ? xm2 : 0.0, Xp2, me,
+                        nullptr);
+        }
+        if (active) gather_store<true>(a, out, o);
+
+        xm2 = prv.X;
+        prv = Nb{cur.r[R_AU], cur.r[R_AV], cur.r[R_AW], cur.r[R_AT], cur.r[R_XZ], cur.r[R_BP], cur.w * Hz};
+        cur = nxt;
+        nxt = nn2;
+        if (k + 3 < nk && k + 1 < k1) load(k + 3, nn2);
+    }
 }
 
 // ---- cotangent of the mean hot-wall Nusselt number ----
@@ -432,9 +680,9 @@ size_t adjoint_ws_doubles(const Dims& d)
     return (size_t)(8 + (part + 7) / 8 * 8 + (long long)NREC * n);
 }
 
-hipError_t launch_adjoint_step(const Dims& d, const Coef& c, const SweepGeom& g, double Ra, CStateT<double> q,
-                               CStateT<double> lam_in, StateT<double> lam_out, double* ws, double* dthot,
-                               double* dra, hipStream_t s)
+hipError_t launch_adjoint_step(const Dims& d, const Coef& c, const SweepGeom& g, const SweepGeom& gg, double Ra,
+                               CStateT<double> q, CStateT<double> lam_in, StateT<double> lam_out, double* ws,
+                               double* dthot, double* dra, hipStream_t s)
 {
     const long long n = (long long)d.ni * d.nj * d.nk;
     const long long rows = (long long)d.nj * d.nk;
@@ -464,12 +712,31 @@ hipError_t launch_adjoint_step(const Dims& d, const Coef& c, const SweepGeom& g,
         sum_kernel<<<1, ADJ_THREADS, 0, s>>>(part, g.nblocks, NF, dra, 1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    // 8 j slabs (one per XCD), as many blocks for each as the widest needs
-    const long long wmax = (d.nj + 7) / 8;
-    const long long per_xcd = ((long long)d.ni * wmax * d.nk + ADJ_THREADS - 1) / ADJ_THREADS;
-    adjoint_gather_kernel<<<(unsigned)(8 * per_xcd), ADJ_THREADS, 0, s>>>(d, c, q, lam_in, psum, rec, lam_out,
-                                                                         dthot);
+    if (gg.kc >= CAV_ADJ_TILE_MIN_KC) {
+        adjoint_gather_tile_kernel<ADJ_GTJ><<<gg.nblocks, dim3(64, ADJ_GTJ), 0, s>>>(d, c, gg, q, lam_in, psum, rec,
+                                                                                 lam_out, dthot);
+    } else {
+        // 8 j slabs (one per XCD), as many blocks for each as the widest needs
+        const long long wmax = (d.nj + 7) / 8;
+        const long long per_xcd = ((long long)d.ni * wmax * d.nk + ADJ_THREADS - 1) / ADJ_THREADS;
+        adjoint_gather_kernel<<<(unsigned)(8 * per_xcd), ADJ_THREADS, 0, s>>>(d, c, q, lam_in, psum, rec, lam_out,
+                                                                             dthot);
+    }
     return hipGetLastError();
+}
+
+SweepGeom gather_geom(const Dims& d, int cus)
+{
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adjoint_gather_tile_kernel<ADJ_GTJ>, 64 * ADJ_GTJ, 0) !=
+                hipSuccess ||
+            n < 1)
+            n = 1;
+        per_cu = n;
+    }
+    return sweep_geom(d, cus * per_cu, 64, ADJ_GTJ);
 }
 
 hipError_t launch_nusselt_seed(const Dims& d, double scale, StateT<double> lam, double* dthot, hipStream_t s)

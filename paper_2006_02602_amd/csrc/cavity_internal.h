@@ -191,10 +191,12 @@ hipError_t launch_split(const Dims& d, const Coef& c, const SweepGeom& gi, const
 
 // Discrete adjoint (FP64): workspace size in doubles, one reverse step, and
 // the cotangent of the mean hot-wall Nusselt number (scale = ni/3/(nj nk dT)).
+// g: the record pass (sweep_geom); gg: the gather (gather_geom).
 size_t adjoint_ws_doubles(const Dims& d);
-hipError_t launch_adjoint_step(const Dims& d, const Coef& c, const SweepGeom& g, double Ra, CStateT<double> q,
-                               CStateT<double> lam_in, StateT<double> lam_out, double* ws, double* dthot,
-                               double* dra, hipStream_t s);
+SweepGeom gather_geom(const Dims& d, int cus);
+hipError_t launch_adjoint_step(const Dims& d, const Coef& c, const SweepGeom& g, const SweepGeom& gg, double Ra,
+                               CStateT<double> q, CStateT<double> lam_in, StateT<double> lam_out, double* ws,
+                               double* dthot, double* dra, hipStream_t s);
 hipError_t launch_nusselt_seed(const Dims& d, double scale, StateT<double> lam, double* dthot, hipStream_t s);
 
 }  // namespace cav

@@ -11,6 +11,10 @@ differentiates with respect to.
     (stored values, 1e-9), and against central finite differences of the
     library's own forward along 16 seeded directions (h = 1e-6, and a
     Richardson extrapolation at h = 1e-5 within the plain 1e-6);
+  * one reverse step with a dense random cotangent against the tangent of
+    one forward step (both gather kernels, 1e-11 of the inner products'
+    absolute sums), and at 256^3 on the gather tile's edges against central
+    differences of the forward step (1e-6);
   * checkpoint interval and in-place cotangents change nothing (bit-exact);
   * the torch.autograd wrapper returns the same gradient.
 """
@@ -221,6 +225,108 @@ def test_gradient_matches_finite_differences_64(C):
         assert abs(got - fd6) <= 1e-6 * abs(fd6) + 1e-14 * abs(J) / 1e-6
         assert eR <= 1e-6, (name, got, rich)
     say("  worst rel: fd h=1e-6 %.2e, richardson %.2e" % (worst6, worstR))
+
+
+def _reverse_step(C, g, prm, q, lam):
+    import torch
+    out = torch.full_like(lam, float("nan"))
+    ws = torch.empty(C.cavity_adjoint_workspace_bytes(g) // 8, dtype=torch.float64, device="cuda")
+    dth = torch.zeros(g.nj * g.nk, dtype=torch.float64, device="cuda")
+    dra = torch.zeros(1, dtype=torch.float64, device="cuda")
+    C.cavity_adjoint_step(g, prm, q, lam, out, ws, dth, dra)
+    torch.cuda.synchronize()
+    return out, dth.cpu().numpy(), float(dra.cpu()[0])
+
+
+@pytest.mark.parametrize("n,Ra", [((130, 130, 40), 1e5), ((67, 37, 21), 1e6)])
+def test_reverse_step_dense_cotangent_matches_tangent(C, n, Ra):
+    """One reverse step with a dense random cotangent lam against the
+    complex-step tangent of one forward step: <lam_out, v> = <lam, J v>
+    along a random state direction, and the wall and Ra parts likewise.
+    The Nusselt gradients above start from a cotangent that is zero away
+    from the hot wall; this one reaches every cell, so every neighbour the
+    gather reads matters.  130 x 130 x 40 on 256 compute units runs the LDS
+    tile gather (k chunks of 8 planes, ragged i and j tiles); 67 x 37 x 21
+    the one-cell-per-thread gather (chunks of 2)."""
+    import torch
+    say("reverse step vs tangent, dense cotangent", n, Ra)
+    ni, nj, nk = n
+    P = O.Problem(*n)
+    theta = theta_of(n, 9)
+    q0 = O.init(P, 5, 1e-2)
+    rng = np.random.default_rng(3)
+    lam_in = np.zeros_like(q0)
+    P.interior(lam_in)[:] = rng.standard_normal((5, nk, nj, ni))
+    g = C.Grid(*n)
+    prm = C.Params(Ra=Ra, t_hot_field=torch.from_numpy(theta).cuda())
+    out, dth, dra = _reverse_step(C, g, prm, gpu_state(C, g, q0), gpu_state(C, g, lam_in))
+    lam_out = interior_np(C, g, out)
+    assert np.isfinite(lam_out).all()
+    L = P.interior(lam_in)
+
+    def tangent(dq=None, dtheta=None, dRa=0.0):
+        h = TG.H_STEP
+        zq = q0.astype(np.complex128)
+        if dq is not None:
+            zq = zq + 1j * h * dq
+        zt = theta.astype(np.complex128)
+        if dtheta is not None:
+            zt = zt + 1j * h * dtheta
+        Jv = TG.step(TG.Case(ni, nj, nk, complex(Ra, h * dRa), zt), zq).imag / h
+        Jv = Jv[:, 2:2 + nk, 2:2 + nj, 2:2 + ni]
+        return float(np.sum(L * Jv)), float(np.sum(np.abs(L * Jv)))
+
+    dq = np.zeros_like(q0)
+    P.interior(dq)[:] = rng.uniform(-1, 1, (5, nk, nj, ni))
+    dt = rng.uniform(-1, 1, nj * nk)
+    for name, kw, got in (("q", dict(dq=dq), float(np.sum(lam_out * P.interior(dq)))),
+                          ("theta", dict(dtheta=dt), float(dth @ dt)),
+                          ("Ra", dict(dRa=Ra), dra * Ra)):
+        want, scale = tangent(**kw)
+        say("  %-5s adjoint % .15e tangent % .15e" % (name, got, want))
+        assert abs(got - want) <= 1e-11 * scale, (name, got, want, scale)
+
+
+def test_reverse_step_full_size_tile_edges(C):
+    """256^3 in the launch the reverse step is timed in: lam_out at cells on
+    the edges of the gather's LDS tiles (i = 63, 64, 191, 192; j = 7, 8;
+    the k chunk edge 127, 128), at walls and corners, against central
+    differences of the library's own forward step (cavity_step_from) along
+    those cells: sum(lam * (step(q + h e) - step(q - h e))) / (2 h).  Away
+    from the cell's star the two steps agree bit for bit, so the sum holds
+    only the star's terms; h = 1e-6 keeps truncation (h^2) and rounding
+    (eps / h) near 1e-10 of the derivative."""
+    import torch
+    say("reverse step 256^3, tile edges vs central differences")
+    g = C.Grid.cube(256)
+    G = g.ng
+    prm = C.Params(Ra=1e5)
+    q = torch.zeros(C.cavity_state_elems(g), dtype=torch.float64, device="cuda")
+    C.cavity_init(g, prm, 4, 1e-2, q)
+    gen = torch.Generator(device="cuda").manual_seed(17)
+    lam = torch.randn(C.cavity_state_elems(g), generator=gen, dtype=torch.float64, device="cuda")
+    out, _, _ = _reverse_step(C, g, prm, q, lam)
+    lv, ov = C.state_view(g, lam), C.state_view(g, out)
+    inner = (slice(None), slice(G, G + 256), slice(G, G + 256), slice(G, G + 256))
+    assert bool(torch.isfinite(ov[inner]).all())
+    cells = [(0, 63, 7, 127), (1, 64, 8, 128), (2, 191, 7, 128), (3, 192, 8, 127), (4, 64, 7, 127),
+             (0, 192, 255, 0), (1, 0, 8, 255), (4, 0, 0, 128), (2, 255, 7, 64), (3, 63, 0, 200),
+             (4, 255, 255, 255), (0, 1, 128, 1)]
+    h = 1e-6
+    qp, qm = torch.empty_like(q), torch.empty_like(q)
+    a, b = torch.empty_like(q), torch.empty_like(q)
+    av, bv = C.state_view(g, a), C.state_view(g, b)
+    for f, i, j, k in cells:
+        qp.copy_(q)
+        qm.copy_(q)
+        C.state_view(g, qp)[f, G + k, G + j, G + i] += h
+        C.state_view(g, qm)[f, G + k, G + j, G + i] -= h
+        C.cavity_step_from(g, prm, qp, a)
+        C.cavity_step_from(g, prm, qm, b)
+        fd = float(torch.sum(lv[inner] * (av[inner] - bv[inner]))) / (2 * h)
+        got = float(ov[f, G + k, G + j, G + i])
+        say("  field %d cell (%3d %3d %3d): adjoint % .12e  central diff % .12e" % (f, i, j, k, got, fd))
+        assert abs(got - fd) <= 1e-6 * max(abs(fd), 1e-3), (f, i, j, k, got, fd)
 
 
 def test_checkpoint_interval_and_in_place_change_nothing(C):
