@@ -218,8 +218,10 @@ struct RecordEpi {
         double v[NREC], nub, alb, dtvb;
         reverse_record(c, s, a, b, v, nub, alb, dtvb);
         const long long idx = i + (long long)d.ni * (j + (long long)d.nj * k);
+        // streaming stores: the record (88 B per cell) is read back only by
+        // the gather, after the whole pass
 #pragma unroll
-        for (int m = 0; m < NREC; ++m) rec[(size_t)m * n + idx] = v[m];
+        for (int m = 0; m < NREC; ++m) __builtin_nontemporal_store(v[m], &rec[(size_t)m * n + idx]);
         acc[0] += (nub * rf.nu + alb * rf.alpha) + dtvb * rf.dtv;
     }
 };
@@ -545,11 +547,14 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
             hdst[s] = T::at(v, hr, hc);
         }
     }
-    double hv[T::SLOTS];
-    auto load_halo = [&](int k) {
+    // halo values of one plane
+    struct Halo {
+        double v[T::SLOTS];
+    };
+    auto load_halo = [&](int k, Halo& H) {
 #pragma unroll
         for (int s = 0; s < T::SLOTS; ++s)
-            if (hdst[s] >= 0) hv[s] = hsrc[s][k * hstr[s]];
+            if (hdst[s] >= 0) H.v[s] = hsrc[s][k * hstr[s]];
     };
 
     auto R = [&](int v, long long m) { return rec[(size_t)v * n + m]; };
@@ -563,7 +568,6 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
     };
     const int k0 = tb.k0, k1 = tb.k1, nk = d.nk;
     const double Hx = c.hx2, Hy = c.hy2, Hz = c.hz2;
-    Column cur, nxt, nn2;
     Nb prv{0, 0, 0, 0, 0, 0, 0};
     double xm2 = 0.0;
     if (k0 >= 2) xm2 = R(R_XZ, col + (k0 - 2) * plane);
@@ -572,12 +576,22 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
         prv = Nb{R(R_AU, m), R(R_AV, m), R(R_AW, m), R(R_AT, m), R(R_XZ, m), R(R_BP, m),
                  q.f[FW][ocol + (k0 - 1) * Z] * Hz};
     }
-    load(k0, cur);
-    load_halo(k0);
-    if (k0 + 1 < nk) load(k0 + 1, nxt);
-    if (k0 + 2 < nk) load(k0 + 2, nn2);
+    // Three register sets of planes (records and halo) rotate through the
+    // roles k, k+1, k+2, so that no set is copied while its loads are in
+    // flight: each set is loaded three planes before it is the current one,
+    // at the same time as the neighbouring tiles load that plane's cells.
+    Column C0, C1, C2;
+    Halo H0, H1, H2;
+    load(k0, C0);
+    load_halo(k0, H0);
+    if (k0 + 1 < nk) load(k0 + 1, C1);
+    if (k0 + 1 < k1) load_halo(k0 + 1, H1);
+    if (k0 + 2 < nk) load(k0 + 2, C2);
+    if (k0 + 2 < k1) load_halo(k0 + 2, H2);
 
-    for (int k = k0; k < k1; ++k) {
+    // plane k: cur = plane k, nxt = k+1, nn2 = k+2 (only its z dissipation
+    // term is read); cur and H are reloaded with plane k+3 once used
+    auto body = [&](int k, Column& cur, const Column& nxt, const Column& nn2, Halo& H) __attribute__((always_inline)) {
         double* B = L + ((k - k0) & 1) * T::BUF;
         {
             const double own[NLV] = {cur.r[R_AU], cur.r[R_AV], cur.r[R_AW], cur.r[R_AT], cur.r[R_BP],
@@ -587,8 +601,8 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
         }
 #pragma unroll
         for (int s = 0; s < T::SLOTS; ++s)
-            if (hdst[s] >= 0) B[hdst[s]] = hv[s];
-        if (k + 1 < k1) load_halo(k + 1);
+            if (hdst[s] >= 0) B[hdst[s]] = H.v[s];
+        if (k + 3 < k1) load_halo(k + 3, H);
         __syncthreads();
 
         const int o = ocol + k * Z;
@@ -636,9 +650,13 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
 
         xm2 = prv.X;
         prv = Nb{cur.r[R_AU], cur.r[R_AV], cur.r[R_AW], cur.r[R_AT], cur.r[R_XZ], cur.r[R_BP], cur.w * Hz};
-        cur = nxt;
-        nxt = nn2;
-        if (k + 3 < nk && k + 1 < k1) load(k + 3, nn2);
+        // plane k+3 is read from iteration k+1 on (as its k+2)
+        if (k + 3 < nk && k + 1 < k1) load(k + 3, cur);
+    };
+    for (int k = k0; k < k1; k += 3) {
+        body(k, C0, C1, C2, H0);
+        if (k + 1 < k1) body(k + 1, C1, C2, C0, H1);
+        if (k + 2 < k1) body(k + 2, C2, C0, C1, H2);
     }
 }
 
