@@ -141,35 +141,11 @@ __device__ __forceinline__ void reverse_record(const CoefR<double>& c, const Sta
 
 __device__ __forceinline__ int centre_off(const Dims& d) { return cell_off(d, d.ni / 2, d.nj / 2, d.nk / 2); }
 
-// ---- 1. sum of lambda_p over the interior, fixed order ----
-// Stage 1: block b sums the interior cells of rows [b*rpb, (b+1)*rpb) (row
-// = (j, k)), the threads striding over the group's cells with i fastest so
-// that loads are coalesced; a fixed tree per block writes part[b].
-__global__ __launch_bounds__(ADJ_THREADS) void row_sum_kernel(Dims d, int rpb, const double* __restrict__ lp,
-                                                              double* __restrict__ part)
-{
-    __shared__ double red[ADJ_THREADS];
-    const int t = threadIdx.x;
-    const int rows = d.nj * d.nk;
-    const int r0 = blockIdx.x * rpb, r1 = min(r0 + rpb, rows);
-    double acc = 0.0;
-    for (int r = r0; r < r1; ++r) {                      // uniform: row offsets in scalar registers
-        const int o = cell_off(d, 0, r % d.nj, r / d.nj);
-        for (int i = t; i < d.ni; i += ADJ_THREADS) acc += lp[o + i];
-    }
-    red[t] = acc;
-    __syncthreads();
-    for (int w = ADJ_THREADS / 2; w > 0; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
-    }
-    if (t == 0) part[blockIdx.x] = red[0];
-}
-
-// Sum of part[b * stride] for b < n in a fixed order; out[0] = sum (or +=
-// when accumulate).
+// ---- fixed-order sums of per-block partials ----
+// out[0] = sum of part[b * stride] for b < n, plus add[0] when add is not
+// NULL (or out[0] += that when accumulate).
 __global__ __launch_bounds__(ADJ_THREADS) void sum_kernel(const double* __restrict__ part, int n, int stride,
-                                                          double* out, int accumulate)
+                                                          const double* add, double* out, int accumulate)
 {
     __shared__ double red[ADJ_THREADS];
     const int t = threadIdx.x;
@@ -181,7 +157,10 @@ __global__ __launch_bounds__(ADJ_THREADS) void sum_kernel(const double* __restri
         if (t < w) red[t] += red[t + w];
         __syncthreads();
     }
-    if (t == 0) out[0] = accumulate ? out[0] + red[0] : red[0];
+    if (t == 0) {
+        const double v = add ? red[0] + add[0] : red[0];
+        out[0] = accumulate ? out[0] + v : v;
+    }
 }
 
 // ---- 2. record pass ----
@@ -191,19 +170,22 @@ struct RaFactors {
 
 // What the k-marching tile does with each cell: seeds from lambda*, the
 // reverse of the residual, the record stored at the cell's dense index, the
-// Ra term into acc[0].
+// Ra term into acc[0] and lambda_p into acc[1] (the block's share of the
+// sum the centre cell's lambda* needs).  The centre cell itself is left to
+// a second launch (centre >= 0) once that sum is known.
 struct RecordEpi {
     CStateT<double> lam;
     const double* psum;
     double* rec;
     long long n;
     RaFactors rf;
+    bool fix;                  // the centre-cell launch
     double ps;
     int centre;
     __device__ __forceinline__ void prepare(const Dims& d, const CStateT<double>&, const CoefR<double>&)
     {
-        ps = psum[0];
-        centre = centre_off(d);
+        ps = fix ? psum[0] : 0.0;
+        centre = fix ? centre_off(d) : -1;
     }
     __device__ __forceinline__ void cell(const CoefR<double>& c, const Star<double>& s, const double R[NF], double dt,
                                          int o, int i, int j, int k, double acc[NF], const Dims& d)
@@ -211,9 +193,11 @@ struct RecordEpi {
         double a[NF], b = 0.0;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            const double ls = (f == FP && o == centre) ? lam.f[f][o] - ps : lam.f[f][o];
+            const double l = lam.f[f][o];
+            const double ls = (f == FP && o == centre) ? l - ps : l;
             a[f] = ls * dt;
             b = fma(ls, R[f], b);
+            if (f == FP) acc[1] += l;
         }
         double v[NREC], nub, alb, dtvb;
         reverse_record(c, s, a, b, v, nub, alb, dtvb);
@@ -242,6 +226,17 @@ struct RecordEpiD {
     }
 };
 
+// Every cell but (ci, cj, ck), or only that cell.
+template <bool ONLY>
+struct OwnCentre {
+    int ci, cj, ck;
+    __device__ __forceinline__ bool operator()(int i, int j, int k) const
+    {
+        return (i == ci && j == cj && k == ck) == ONLY;
+    }
+    __device__ __forceinline__ bool column(int, int) const { return true; }
+};
+
 __global__ __launch_bounds__(SW_TI * SW_TJ) void record_kernel(Dims d, Coef cd, SweepGeom g, RaFactors rf,
                                                                CStateT<double> q, CStateT<double> lam,
                                                                const double* psum, double* rec, double* partials)
@@ -249,8 +244,29 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void record_kernel(Dims d, Coef cd, 
     __shared__ SweepLds<double> L;
     const CoefR<double> c = coef_as<double>(cd);
     const TileBox tb = tile_box(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
-    RecordEpiD epi{{lam, psum, rec, (long long)d.ni * d.nj * d.nk, rf, 0.0, 0}, d};
-    sweep_tile<double, true, OwnAll, RecordEpiD, 2>(d, c, tb, OwnAll{}, q, epi, partials, L);
+    RecordEpiD epi{{lam, psum, rec, (long long)d.ni * d.nj * d.nk, rf, false, 0.0, -1}, d};
+    sweep_tile<double, true, OwnCentre<false>, RecordEpiD, 2>(d, c, tb, OwnCentre<false>{d.ni / 2, d.nj / 2, d.nk / 2},
+                                                              q, epi, partials, L);
+}
+
+// The centre cell's record, with lambda*_p = lambda_p - sum(lambda_p): one
+// block, the tile holding the centre, its plane only; partial slot pidx.
+__global__ __launch_bounds__(SW_TI * SW_TJ) void record_centre_kernel(Dims d, Coef cd, RaFactors rf, CStateT<double> q,
+                                                                      CStateT<double> lam, const double* psum,
+                                                                      double* rec, double* partials, int pidx)
+{
+    __shared__ SweepLds<double> L;
+    const CoefR<double> c = coef_as<double>(cd);
+    const int ci = d.ni / 2, cj = d.nj / 2, ck = d.nk / 2;
+    TileBox tb;
+    tb.i0 = ci / SW_TI * SW_TI;
+    tb.j0 = cj / SW_TJ * SW_TJ;
+    tb.k0 = ck;
+    tb.k1 = ck + 1;
+    tb.pidx = pidx;
+    RecordEpiD epi{{lam, psum, rec, (long long)d.ni * d.nj * d.nk, rf, true, 0.0, -1}, d};
+    sweep_tile<double, true, OwnCentre<true>, RecordEpiD, 2>(d, c, tb, OwnCentre<true>{ci, cj, ck}, q, epi, partials,
+                                                             L);
 }
 
 // What the gather needs from a neighbour m one cell away along an axis:
@@ -680,11 +696,12 @@ __global__ __launch_bounds__(ADJ_THREADS) void nusselt_seed_kernel(Dims d, doubl
 }
 
 // Partials of the record pass: one per block of any k-chunk tiling (the
-// chunking never yields more than nk/CAV_MIN_KC chunks per tile column), NF each.
+// chunking never yields more than nk/CAV_MIN_KC chunks per tile column),
+// plus one for the centre-cell launch, NF each.
 long long record_partials(const Dims& d)
 {
     const long long tiles = (long long)((d.ni + SW_TI - 1) / SW_TI) * ((d.nj + SW_TJ - 1) / SW_TJ);
-    return tiles * std::max(1, d.nk / CAV_MIN_KC) * NF;
+    return (tiles * std::max(1, d.nk / CAV_MIN_KC) + 1) * NF;
 }
 
 }  // namespace
@@ -693,41 +710,35 @@ long long record_partials(const Dims& d)
 size_t adjoint_ws_doubles(const Dims& d)
 {
     const long long n = (long long)d.ni * d.nj * d.nk;
-    const long long rows = (long long)d.nj * d.nk;
-    const long long part = std::max(std::min(rows, 1024LL), record_partials(d));
-    return (size_t)(8 + (part + 7) / 8 * 8 + (long long)NREC * n);
+    return (size_t)(8 + (record_partials(d) + 7) / 8 * 8 + (long long)NREC * n);
 }
 
 hipError_t launch_adjoint_step(const Dims& d, const Coef& c, const SweepGeom& g, const SweepGeom& gg, double Ra,
                                CStateT<double> q, CStateT<double> lam_in, StateT<double> lam_out, double* ws,
                                double* dthot, double* dra, hipStream_t s)
 {
-    const long long n = (long long)d.ni * d.nj * d.nk;
-    const long long rows = (long long)d.nj * d.nk;
     double* psum = ws;                       // ws[0]: sum of lambda_p
     double* part = ws + 8;
-    const long long np = std::max(std::min(rows, 1024LL), record_partials(d));
+    const long long np = record_partials(d);
     double* rec = part + (np + 7) / 8 * 8;
-    if ((long long)g.nblocks * NF > np) return hipErrorInvalidValue;
-    // about 1024 blocks of whole rows, at most one per partial slot
-    const int rpb = (int)std::max(1LL, (rows + 1023) / 1024);
-    const int rb = (int)((rows + rpb - 1) / rpb);
-    if (rb > np) return hipErrorInvalidValue;
+    if ((long long)(g.nblocks + 1) * NF > np) return hipErrorInvalidValue;
     hipError_t e;
-
-    row_sum_kernel<<<rb, ADJ_THREADS, 0, s>>>(d, rpb, lam_in.f[FP], part);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    sum_kernel<<<1, ADJ_THREADS, 0, s>>>(part, rb, 1, psum, 0);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
 
     RaFactors rf;
     rf.nu = -c.nu / (2.0 * Ra);
     rf.alpha = -c.alpha / (2.0 * Ra);
     rf.dtv = c.dt_visc / (2.0 * Ra);
+    // every record but the centre cell's; each block's sum of lambda_p
     record_kernel<<<g.nblocks, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, g, rf, q, lam_in, psum, rec, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    // sum of lambda_p: the blocks' sums in order, then the centre cell's
+    sum_kernel<<<1, ADJ_THREADS, 0, s>>>(part + 1, g.nblocks, NF,
+                                         lam_in.f[FP] + cell_off(d, d.ni / 2, d.nj / 2, d.nk / 2), psum, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    record_centre_kernel<<<1, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, rf, q, lam_in, psum, rec, part, g.nblocks);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (dra) {
-        sum_kernel<<<1, ADJ_THREADS, 0, s>>>(part, g.nblocks, NF, dra, 1);
+        sum_kernel<<<1, ADJ_THREADS, 0, s>>>(part, g.nblocks + 1, NF, nullptr, dra, 1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (gg.kc >= CAV_ADJ_TILE_MIN_KC) {
