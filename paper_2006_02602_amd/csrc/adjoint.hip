@@ -142,25 +142,24 @@ __device__ __forceinline__ void reverse_record(const CoefR<double>& c, const Sta
 __device__ __forceinline__ int centre_off(const Dims& d) { return cell_off(d, d.ni / 2, d.nj / 2, d.nk / 2); }
 
 // ---- fixed-order sums of per-block partials ----
-// out[0] = sum of part[b * stride] for b < n, plus add[0] when add is not
-// NULL (or out[0] += that when accumulate).
-__global__ __launch_bounds__(ADJ_THREADS) void sum_kernel(const double* __restrict__ part, int n, int stride,
-                                                          const double* add, double* out, int accumulate)
+// Sum of part[b * stride] for b < n: thread t < ADJ_THREADS adds b = t,
+// t + ADJ_THREADS, ..., then a fixed tree.  Every thread of the block calls
+// it (it holds barriers) and gets the sum.
+__device__ double block_sum(const double* __restrict__ part, int n, int stride, double* red)
 {
-    __shared__ double red[ADJ_THREADS];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x + blockDim.x * threadIdx.y;
     double acc = 0.0;
-    for (int b = t; b < n; b += ADJ_THREADS) acc += part[(size_t)b * stride];
-    red[t] = acc;
+    if (t < ADJ_THREADS)
+        for (int b = t; b < n; b += ADJ_THREADS) acc += part[(size_t)b * stride];
+    if (t < ADJ_THREADS) red[t] = acc;
     __syncthreads();
     for (int w = ADJ_THREADS / 2; w > 0; w >>= 1) {
         if (t < w) red[t] += red[t + w];
         __syncthreads();
     }
-    if (t == 0) {
-        const double v = add ? red[0] + add[0] : red[0];
-        out[0] = accumulate ? out[0] + v : v;
-    }
+    const double v = red[0];
+    __syncthreads();                      // red may be reused
+    return v;
 }
 
 // ---- 2. record pass ----
@@ -175,16 +174,14 @@ struct RaFactors {
 // a second launch (centre >= 0) once that sum is known.
 struct RecordEpi {
     CStateT<double> lam;
-    const double* psum;
     double* rec;
     long long n;
     RaFactors rf;
     bool fix;                  // the centre-cell launch
-    double ps;
+    double ps;                 // the sum of lambda_p (the centre-cell launch)
     int centre;
     __device__ __forceinline__ void prepare(const Dims& d, const CStateT<double>&, const CoefR<double>&)
     {
-        ps = fix ? psum[0] : 0.0;
         centre = fix ? centre_off(d) : -1;
     }
     __device__ __forceinline__ void cell(const CoefR<double>& c, const Star<double>& s, const double R[NF], double dt,
@@ -238,35 +235,47 @@ struct OwnCentre {
 };
 
 __global__ __launch_bounds__(SW_TI * SW_TJ) void record_kernel(Dims d, Coef cd, SweepGeom g, RaFactors rf,
-                                                               CStateT<double> q, CStateT<double> lam,
-                                                               const double* psum, double* rec, double* partials)
+                                                               CStateT<double> q, CStateT<double> lam, double* rec,
+                                                               double* partials)
 {
     __shared__ SweepLds<double> L;
     const CoefR<double> c = coef_as<double>(cd);
     const TileBox tb = tile_box(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
-    RecordEpiD epi{{lam, psum, rec, (long long)d.ni * d.nj * d.nk, rf, false, 0.0, -1}, d};
+    RecordEpiD epi{{lam, rec, (long long)d.ni * d.nj * d.nk, rf, false, 0.0, -1}, d};
     sweep_tile<double, true, OwnCentre<false>, RecordEpiD, 2>(d, c, tb, OwnCentre<false>{d.ni / 2, d.nj / 2, d.nk / 2},
                                                               q, epi, partials, L);
 }
 
-// The centre cell's record, with lambda*_p = lambda_p - sum(lambda_p): one
-// block, the tile holding the centre, its plane only; partial slot pidx.
+// After the record pass, one block: the sum of lambda_p (the record blocks'
+// sums in a fixed order, then the centre cell's), stored for the gather;
+// the centre cell's record with lambda*_p = lambda_p - that sum (the tile
+// holding the centre, its plane only; partial slot nblocks); then, if dra
+// is not NULL, dra += the Ra partials of all nblocks + 1 slots in a fixed
+// order.
 __global__ __launch_bounds__(SW_TI * SW_TJ) void record_centre_kernel(Dims d, Coef cd, RaFactors rf, CStateT<double> q,
-                                                                      CStateT<double> lam, const double* psum,
-                                                                      double* rec, double* partials, int pidx)
+                                                                      CStateT<double> lam, double* psum, double* rec,
+                                                                      double* partials, int nblocks, double* dra)
 {
     __shared__ SweepLds<double> L;
+    __shared__ double red[ADJ_THREADS];
     const CoefR<double> c = coef_as<double>(cd);
     const int ci = d.ni / 2, cj = d.nj / 2, ck = d.nk / 2;
+    const double ps = block_sum(partials + 1, nblocks, NF, red) + lam.f[FP][cell_off(d, ci, cj, ck)];
+    if (threadIdx.x == 0 && threadIdx.y == 0) psum[0] = ps;
     TileBox tb;
     tb.i0 = ci / SW_TI * SW_TI;
     tb.j0 = cj / SW_TJ * SW_TJ;
     tb.k0 = ck;
     tb.k1 = ck + 1;
-    tb.pidx = pidx;
-    RecordEpiD epi{{lam, psum, rec, (long long)d.ni * d.nj * d.nk, rf, true, 0.0, -1}, d};
+    tb.pidx = nblocks;
+    RecordEpiD epi{{lam, rec, (long long)d.ni * d.nj * d.nk, rf, true, ps, -1}, d};
     sweep_tile<double, true, OwnCentre<true>, RecordEpiD, 2>(d, c, tb, OwnCentre<true>{ci, cj, ck}, q, epi, partials,
                                                              L);
+    if (dra) {
+        __syncthreads();                  // this block's partial slot is written
+        const double v = block_sum(partials, nblocks + 1, NF, red);
+        if (threadIdx.x == 0 && threadIdx.y == 0) dra[0] += v;
+    }
 }
 
 // What the gather needs from a neighbour m one cell away along an axis:
@@ -729,18 +738,11 @@ hipError_t launch_adjoint_step(const Dims& d, const Coef& c, const SweepGeom& g,
     rf.alpha = -c.alpha / (2.0 * Ra);
     rf.dtv = c.dt_visc / (2.0 * Ra);
     // every record but the centre cell's; each block's sum of lambda_p
-    record_kernel<<<g.nblocks, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, g, rf, q, lam_in, psum, rec, part);
+    record_kernel<<<g.nblocks, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, g, rf, q, lam_in, rec, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // sum of lambda_p: the blocks' sums in order, then the centre cell's
-    sum_kernel<<<1, ADJ_THREADS, 0, s>>>(part + 1, g.nblocks, NF,
-                                         lam_in.f[FP] + cell_off(d, d.ni / 2, d.nj / 2, d.nk / 2), psum, 0);
+    // the sum of lambda_p, the centre cell's record, the Ra cotangent
+    record_centre_kernel<<<1, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, rf, q, lam_in, psum, rec, part, g.nblocks, dra);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    record_centre_kernel<<<1, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, rf, q, lam_in, psum, rec, part, g.nblocks);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (dra) {
-        sum_kernel<<<1, ADJ_THREADS, 0, s>>>(part, g.nblocks + 1, NF, nullptr, dra, 1);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
     if (gg.kc >= CAV_ADJ_TILE_MIN_KC) {
         adjoint_gather_tile_kernel<ADJ_GTJ><<<gg.nblocks, dim3(64, ADJ_GTJ), 0, s>>>(d, c, gg, q, lam_in, psum, rec,
                                                                                  lam_out, dthot);
