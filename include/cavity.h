@@ -300,7 +300,8 @@ int cavity_nusselt_adjoint(const cav_grid* grid, const cav_params* prm, void* la
  * step's terms into dj_dthot (device, nj*nk doubles, j fastest) and dj_dra
  * (device, 1 double); either may be NULL to skip it.  lam_out may equal
  * lam_in; neither may alias q_n.  ws: device, >=
- * cavity_adjoint_workspace_bytes.  Five launches on `stream`, no
+ * cavity_adjoint_workspace_bytes.  Three launches on `stream` (the record
+ * pass, one block for the centre cell and the sums, the gather), no
  * allocation, no synchronisation.  CAV_EINVAL for a CAV_F32 grid. */
 int cavity_adjoint_step(const cav_grid* grid, const cav_params* prm,
                         const void* q_n, const void* lam_in, void* lam_out,
