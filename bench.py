@@ -54,9 +54,41 @@ def counter_traffic(kernel_hash):
     return float(m_bytes.group(1))
 
 
+def halo_source_hash():
+    h = hashlib.sha256()
+    for f in ("halo.hip", "halo_layout.h"):
+        with open(os.path.join(ROOT, "paper_2006_02602_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def halo_counter_bytes():
+    """HBM bytes (read + write) per pack/unpack launch by split, widths,
+    mode and kernel, from the committed rocprofv3 counter summary, if it was
+    taken on the current halo source; else {}."""
+    path = os.path.join(ROOT, "profiles", "halo_pack_unpack_cavity256_f64_counters.md")
+    if not os.path.exists(path):
+        return {}
+    text = open(path).read()
+    m = re.search(r"halo source hash[^`]*`([0-9a-f]+)`", text)
+    if not m or m.group(1) != halo_source_hash():
+        return {}
+    out = {}
+    for line in text.splitlines():
+        c = [x.strip() for x in line.strip().strip("|").split("|")]
+        if len(c) < 9 or not re.fullmatch(r"\d+x\d+x\d+", c[0]):
+            continue
+        try:
+            out[(c[0], c[1].replace(" ", ""), c[2], c[3])] = float(c[7]) + float(c[8])
+        except ValueError:
+            continue
+    return out
+
+
 def halo_bench(C, torch, grid, cav, splits, widths_list, reps):
     """Warm and cold (after a 1 GiB flush write) pack/unpack timings."""
     out = []
+    counted = halo_counter_bytes()
     flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
     for split in splits:
         for widths in widths_list:
@@ -82,6 +114,12 @@ def halo_bench(C, torch, grid, cav, splits, widths_list, reps):
                     us = 1e3 * ms / n
                     res["%s_%s_us" % (k.split("_")[1], mode)] = round(us, 2)
                     res["%s_%s_GBs" % (k.split("_")[1], mode)] = round(16.0 * elems / (us * 1e-6) / 1e9, 1)
+                    key = ("x".join(map(str, split)), ",".join(map(str, widths)), mode, k.split("_")[1])
+                    if key in counted:
+                        # HBM bytes by the counters (profiles/) over this run's launch time
+                        gbs = counted[key] / (us * 1e-6) / 1e9
+                        res["%s_%s_counter_GBs" % (k.split("_")[1], mode)] = round(gbs, 1)
+                        res["%s_%s_counter_frac" % (k.split("_")[1], mode)] = round(gbs / HBM_PEAK_GBS, 3)
             out.append(res)
             del buf
     del flush
