@@ -54,6 +54,29 @@ def counter_traffic(kernel_hash):
     return float(m_bytes.group(1))
 
 
+def f32_batch_counter_bytes():
+    """HBM bytes (read + write) per launch of the 384^3 FP32 sweep and per
+    batch step, from the committed rocprofv3 counter summary, if it was taken
+    on the current sweep source; else {}."""
+    path = os.path.join(ROOT, "profiles", "sweep_f32_batch_counters.md")
+    if not os.path.exists(path):
+        return {}
+    text = open(path).read()
+    m = re.search(r"sweep source hash:\s*`?([0-9a-f]+)", text)
+    if not m or m.group(1) != sweep_source_hash():
+        return {}
+    out = {}
+    for line in text.splitlines():
+        c = [x.strip() for x in line.strip().strip("|").split("|")]
+        if len(c) < 3:
+            continue
+        key = ("f32_sweep" if c[0].startswith("`sweep_kernel<float, false") else
+               "batch" if c[0].startswith("`batch_kernel<float, false>") else None)
+        if key:
+            out[key] = float(c[1]) + float(c[2])
+    return out
+
+
 def halo_source_hash():
     h = hashlib.sha256()
     for f in ("halo.hip", "halo_layout.h"):
@@ -165,6 +188,11 @@ def f32_leg(C, torch, steps, with_oracle=True):
                        "GBs": 40.0 * ncell / (sc_us * 1e-6) / 1e9, "frac": 40.0 * ncell / (sc_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
                        "sweep_over_ceiling_time": 1e3 * sw_ms / sc_us},
            "residual_norms_f64": cav.norms(), "nusselt_f64": cav.nusselt()}
+    counted = f32_batch_counter_bytes().get("f32_sweep")
+    if counted:
+        # HBM bytes by the counters (profiles/) over this run's sweep time
+        out["sweep_counter_GBs"] = counted / (sw_ms * 1e-3) / 1e9
+        out["sweep_counter_frac"] = out["sweep_counter_GBs"] / HBM_PEAK_GBS
     del cav
     # accuracy: FP32 vs FP64 GPU from the same start, 128^3, 100 steps
     m = 128
@@ -240,7 +268,8 @@ def batch_leg(C, torch, steps, with_oracle=True):
         gr.destroy()
     norms_ok = all(all(x == x and abs(x) < 1e30 for x in b.norms(m)) for m in range(len(b)))
     acc = batch_vs_oracle(C, torch, b, wl, steps, nb) if with_oracle else None
-    return {"workload": "batch96_f32_edges24-96_ra1e3-1e6", "members": len(b), "cells": b.cells,
+    counted = f32_batch_counter_bytes().get("batch")
+    res = {"workload": "batch96_f32_edges24-96_ra1e3-1e6", "members": len(b), "cells": b.cells,
             "steps": steps, "value": b.cells * steps / dt, "unit": "grid-point updates/s",
             "ms_per_step": 1e3 * dt / steps, "launch": "one persistent kernel per step, %d steps in one HIP graph" % steps,
             "autotuned_tile_and_kc_per_edge": {str(k): {"tile": "%dx%d" % C.batch_tile(C.CAV_F32, v[0]), "kc": v[1]}
@@ -251,6 +280,12 @@ def batch_leg(C, torch, steps, with_oracle=True):
             "bytes_per_step_algorithmic": 40 * b.cells,
             "GBs_algorithmic": 40 * b.cells / (dt / steps) / 1e9, "norms_finite": norms_ok,
             "rel_err_vs_f64_oracle_sampled": acc}
+    if counted:
+        # HBM bytes per step by the counters (profiles/, taken at that run's
+        # tuned shapes) over this run's time per step
+        res["counter_GBs"] = counted / (dt / steps) / 1e9
+        res["counter_frac"] = res["counter_GBs"] / HBM_PEAK_GBS
+    return res
 
 
 def batch_vs_oracle(C, torch, b, wl, steps, nb):
