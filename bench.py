@@ -77,6 +77,28 @@ def f32_batch_counter_bytes():
     return out
 
 
+def adjoint_source_hash():
+    h = hashlib.sha256()
+    for f in ("adjoint.hip", "sweep_tile.h", "stencil.h", "cavity_internal.h"):
+        with open(os.path.join(ROOT, "paper_2006_02602_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def adjoint_counter_bytes():
+    """HBM bytes per 256^3 reverse step from the committed rocprofv3 counter
+    summary, if it was taken on the current adjoint source; else None."""
+    path = os.path.join(ROOT, "profiles", "adjoint_cavity256_f64_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"adjoint source hash[^`]*`([0-9a-f]+)`", text)
+    m_bytes = re.search(r"calibrated HBM bytes per 256\^3 reverse step[^:]*:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != adjoint_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
 def halo_source_hash():
     h = hashlib.sha256()
     for f in ("halo.hip", "halo_layout.h"):
@@ -432,6 +454,11 @@ def adjoint_leg(C, torch):
     out["reverse_step_256cubed_us"] = us
     out["reverse_step_256cubed_GBs_min_traffic"] = ADJ_MIN_BYTES_PER_CELL * cells / (us * 1e-6) / 1e9
     out["reverse_step_min_bytes_per_cell"] = ADJ_MIN_BYTES_PER_CELL
+    counted = adjoint_counter_bytes()
+    if counted:
+        # HBM bytes per reverse step by the counters (profiles/) over this run's time
+        out["reverse_step_256cubed_counter_GBs"] = counted / (us * 1e-6) / 1e9
+        out["reverse_step_256cubed_counter_frac"] = out["reverse_step_256cubed_counter_GBs"] / HBM_PEAK_GBS
     del aws, lam, q
     return out
 
