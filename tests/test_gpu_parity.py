@@ -362,6 +362,42 @@ def test_y_mirror_symmetry_full_size(C):
     assert all(math.isfinite(x) for x in cav.norms())
 
 
+@pytest.mark.parametrize("n,dtype", [(1278, 0), (1274, 1)])
+def test_largest_grid_mirror_symmetry(C, n, dtype):
+    """The largest accepted cubes (one field just below 2^31 elements, so the
+    kernels' 32-bit cell offsets reach their limit; an FP64 state is 85 GB):
+    from a seeded start made y-mirror-symmetric on the device, 2 steps with
+    the 2x2x2 exchange stay symmetric bit for bit and finite.  A wrong or
+    overflowing offset anywhere in the sweep or the exchange breaks the
+    symmetry where it strikes."""
+    import torch
+    say("largest grid", n, "dtype", dtype)
+    g = C.Grid.cube(n, dtype)
+    assert C.cavity_layout(g).sf > 2 ** 31 - 3 * (n + 4) ** 2 * 16
+    cav = C.Cavity(g, C.Params(Ra=1e5), C.Halo((2, 2, 2), (1, 2, 2, 2, 2))).init(2)
+    G, half = 2, n // 2
+    V = C.state_view(g, cav.q)
+    with torch.no_grad():
+        for f in range(5):
+            s = -1.0 if f == 2 else 1.0
+            I = V[f, G:G + n, G:G + n, G:G + n]
+            I[:, n - half:, :] = s * torch.flip(I[:, :half, :], dims=[1])
+    torch.cuda.synchronize()
+    say("  symmetric start set")
+    cav.step(2)
+    torch.cuda.synchronize()
+    say("  stepped")
+    V = C.state_view(g, cav.q)
+    for f in range(5):
+        s = -1.0 if f == 2 else 1.0
+        I = V[f, G:G + n, G:G + n, G:G + n]
+        assert bool(torch.isfinite(I).all()), f
+        assert torch.equal(I, s * torch.flip(I, dims=[1])), f
+    assert all(math.isfinite(x) for x in cav.norms())
+    del cav, V, I
+    torch.cuda.empty_cache()
+
+
 def test_determinism_and_restart(C):
     say("determinism")
     P, g, prm = problem(C, (48, 40, 33), Ra=1e4)
