@@ -338,6 +338,10 @@ typedef struct {
     int32_t members, items, dtype;
     int32_t parity;         /* 0: newest states in q, 1: in q_tmp            */
     uint64_t cells;         /* interior cells over all members               */
+    int32_t shapes;         /* tile shapes among the members: 1 the wide one
+                               only, 2 the narrow one only, 3 both (a batch
+                               of one shape runs a kernel compiled for it)   */
+    int32_t reserved;
 } cav_batch;
 
 /* Bytes of the device table for these members (host array of n). */

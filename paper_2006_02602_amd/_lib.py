@@ -61,7 +61,8 @@ class CavBatchMember(ctypes.Structure):
 
 class CavBatch(ctypes.Structure):
     _fields_ = [("table", ctypes.c_void_p), ("members", ctypes.c_int32), ("items", ctypes.c_int32),
-                ("dtype", ctypes.c_int32), ("parity", ctypes.c_int32), ("cells", ctypes.c_uint64)]
+                ("dtype", ctypes.c_int32), ("parity", ctypes.c_int32), ("cells", ctypes.c_uint64),
+                ("shapes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CavKernelTime(ctypes.Structure):

@@ -25,7 +25,7 @@ from . import BATCH_TILE_WIDTHS, Batch, Grid, Params
 
 KC_CANDIDATES = (4, 8, 16, 32, 0)        # 0 = whole columns (the cavity height per item)
 BLOCK_CANDIDATES = (256, 512, 768, 1024)
-CACHE_VERSION = 2                        # bump when the tile shapes change
+CACHE_VERSION = 3                        # bump when the tile shapes or batch kernels change
 
 
 def ti_candidates(dtype):

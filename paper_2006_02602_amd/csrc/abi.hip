@@ -319,7 +319,7 @@ hipError_t batch_launches(const cav_batch& b, int32_t nsteps, int nblocks, int p
     hipError_t e = hipSuccess;
     for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
         const bool last = n == nsteps - 1;
-        auto go = [&] { return launch_batch<Real>(cavs, segs, items, parity, last, nblocks, stream); };
+        auto go = [&] { return launch_batch<Real>(cavs, segs, items, parity, last, nblocks, b.shapes, stream); };
         e = timed ? run(last ? "batch_norm" : "batch", stream, go) : go();
         parity ^= 1;
     }
@@ -912,6 +912,9 @@ int cavity_batch_build(int32_t n, const cav_batch_member* members, void* table, 
     out->dtype = dtype;
     out->parity = 0;
     out->cells = cells;
+    out->shapes = 0;
+    for (int m = 0; m < n; ++m) out->shapes |= member_ti(members[m]) == batch_wide_ti(dtype == CAV_F32) ? 1 : 2;
+    out->reserved = 0;
     return CAV_OK;
 }
 

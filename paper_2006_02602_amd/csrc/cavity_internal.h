@@ -170,8 +170,9 @@ template <typename Real>
 hipError_t launch_halo(const Dims& d, const HaloGeom& h, StateT<Real> q, Real* buf, bool pack,
                        hipStream_t s, int first_axis = 0);
 template <typename Real>
+// shapes: the tile shapes among the members (1 wide, 2 narrow, 3 both)
 hipError_t launch_batch(const BatchCav* cavs, const int* segs, const BatchItem* items, int parity, bool with_norm,
-                        int nblocks, hipStream_t s);
+                        int nblocks, int shapes, hipStream_t s);
 hipError_t launch_batch_norms(const BatchCav* cavs, int members, hipStream_t s);
 template <typename Real>
 hipError_t launch_nusselt(const Dims& d, const Bcs& b, CStateT<Real> q, double* out,

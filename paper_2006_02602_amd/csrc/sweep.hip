@@ -458,6 +458,9 @@ struct BatchTiles {
     static constexpr int NTI = batch_narrow_ti(F32), NTJ = batch_tj(F32, NTI);
     // prefetch depth: the FP64 kernel would spill a third register set
     static constexpr int DEPTH = F32 ? 3 : 2;
+    // waves per SIMD the one-shape FP32 kernels must fit (three 256-thread
+    // blocks per CU, as the FP32 step sweep; 0: the compiler's choice)
+    static constexpr int MINW1 = F32 ? 3 : 0;
 };
 
 // The item walk of one block: with at least BATCH_SEGS blocks, block b
@@ -477,16 +480,19 @@ __device__ __forceinline__ void for_each_item(const int* __restrict__ segs, F&& 
     }
 }
 
-template <typename Real, bool NORM>
-__global__ __launch_bounds__(BatchTiles<Real>::THREADS) void batch_kernel(const BatchCav* __restrict__ cavs,
-                                                                          const int* __restrict__ segs,
-                                                                          const BatchItem* __restrict__ items,
-                                                                          int parity)
+// SHAPES: 3 = each member's tile shape (both compiled in: the registers of
+// the larger, two blocks per CU in FP32), 1 = the wide shape only, 2 = the
+// narrow one only (one shape: three blocks per CU in FP32).
+template <typename Real, bool NORM, int SHAPES>
+__global__ __launch_bounds__(BatchTiles<Real>::THREADS, SHAPES == 3 ? 0 : BatchTiles<Real>::MINW1) void batch_kernel(
+    const BatchCav* __restrict__ cavs, const int* __restrict__ segs, const BatchItem* __restrict__ items, int parity)
 {
     using BT = BatchTiles<Real>;
+    using Wide = SweepLds<Real, BT::WTI, BT::WTJ>;
+    using Narrow = SweepLds<Real, BT::NTI, BT::NTJ>;
     __shared__ union {
-        SweepLds<Real, BT::WTI, BT::WTJ> wide;
-        SweepLds<Real, BT::NTI, BT::NTJ> narrow;
+        Wide wide;
+        Narrow narrow;
     } L;
     for_each_item(segs, [&](int it) {
         const BatchItem w = items[it];
@@ -503,7 +509,7 @@ __global__ __launch_bounds__(BatchTiles<Real>::THREADS) void batch_kernel(const 
             qn.f[f] = nxt + f * cv.fstride;
         }
         StepEpi<Real> epi{qn, Real(0)};
-        if (cv.ti == BT::NTI) {
+        if (SHAPES == 2 || (SHAPES == 3 && cv.ti == BT::NTI)) {
             const TileBox tb = tile_box<BT::NTI, BT::NTJ>(d, cv.tiles_i, cv.tiles_j, cv.kc, w.tile);
             sweep_tile<Real, NORM, OwnAll, StepEpi<Real>, BT::DEPTH, BT::NTI, BT::NTJ>(
                 d, c, tb, OwnAll{}, qs, epi, cv.ws + WS_HEAD_DOUBLES, L.narrow);
@@ -518,17 +524,24 @@ __global__ __launch_bounds__(BatchTiles<Real>::THREADS) void batch_kernel(const 
 
 template <typename Real>
 hipError_t launch_batch(const BatchCav* cavs, const int* segs, const BatchItem* items, int parity, bool with_norm,
-                        int nblocks, hipStream_t s)
+                        int nblocks, int shapes, hipStream_t s)
 {
     dim3 block(SW_TI, BatchTiles<Real>::THREADS / SW_TI), grid(nblocks);
-    if (with_norm)
-        batch_kernel<Real, true><<<grid, block, 0, s>>>(cavs, segs, items, parity);
-    else
-        batch_kernel<Real, false><<<grid, block, 0, s>>>(cavs, segs, items, parity);
+#define BATCH_LAUNCH(SH)                                                                      \
+    do {                                                                                      \
+        if (with_norm) batch_kernel<Real, true, SH><<<grid, block, 0, s>>>(cavs, segs, items, parity);  \
+        else batch_kernel<Real, false, SH><<<grid, block, 0, s>>>(cavs, segs, items, parity);           \
+    } while (0)
+    if (shapes == 1) BATCH_LAUNCH(1);
+    else if (shapes == 2) BATCH_LAUNCH(2);
+    else BATCH_LAUNCH(3);
+#undef BATCH_LAUNCH
     return hipGetLastError();
 }
-template hipError_t launch_batch<double>(const BatchCav*, const int*, const BatchItem*, int, bool, int, hipStream_t);
-template hipError_t launch_batch<float>(const BatchCav*, const int*, const BatchItem*, int, bool, int, hipStream_t);
+template hipError_t launch_batch<double>(const BatchCav*, const int*, const BatchItem*, int, bool, int, int,
+                                         hipStream_t);
+template hipError_t launch_batch<float>(const BatchCav*, const int*, const BatchItem*, int, bool, int, int,
+                                        hipStream_t);
 
 // Residual norms of every member: one block per member, the same
 // fixed-order reduction as the single-cavity finalize.

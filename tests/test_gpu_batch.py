@@ -80,20 +80,29 @@ def test_batch_result_is_independent_of_k_chunks(C):
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_batch_result_is_independent_of_tile_shape(C, dtype):
     """The narrow tile (FP64 32 x 16, FP32 16 x 16) gives the same states as
-    the wide one (FP64 64 x 8, FP32 32 x 8) and as the single cavity, bit
-    for bit; norms to rounding."""
+    the wide one (FP64 64 x 8, FP32 32 x 8), and so does a batch mixing
+    both, bit for bit; norms to rounding."""
     wide, narrow = C.BATCH_TILE_WIDTHS[dtype]
     say("batch tile shape", dtype, wide, narrow)
     a = C.Batch([(C.Grid(*n, dtype=dtype), C.Params(Ra=Ra), 0, wide) for n, Ra in MEMBERS]).init(range(len(MEMBERS)))
     b = C.Batch([(C.Grid(*n, dtype=dtype), C.Params(Ra=Ra), kc, narrow)
                  for (n, Ra), kc in zip(MEMBERS, (0, 5, 8, 3, 16, 0))])
     b.init(range(len(MEMBERS)))
+    # both shapes in one batch (the kernel compiled for both; a batch of one
+    # shape runs the kernel compiled for that shape alone)
+    c = C.Batch([(C.Grid(*n, dtype=dtype), C.Params(Ra=Ra), 0, (wide, narrow)[m % 2])
+                 for m, (n, Ra) in enumerate(MEMBERS)])
+    c.init(range(len(MEMBERS)))
+    assert (a.handle.shapes, b.handle.shapes, c.handle.shapes) == (1, 2, 3)
     a.step(5)
     b.step(5)
+    c.step(5)
     for m, (n, _) in enumerate(MEMBERS):
         g = C.Grid(*n, dtype=dtype)
         assert np.array_equal(interior(C, g, a.state(m)), interior(C, g, b.state(m))), m
+        assert np.array_equal(interior(C, g, a.state(m)), interior(C, g, c.state(m))), m
         np.testing.assert_allclose(b.norms(m), a.norms(m), rtol=1e-12 if dtype == 0 else 1e-5)
+        np.testing.assert_allclose(c.norms(m), a.norms(m), rtol=1e-12 if dtype == 0 else 1e-5)
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
