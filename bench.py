@@ -71,7 +71,7 @@ def f32_batch_counter_bytes():
         if len(c) < 3:
             continue
         key = ("f32_sweep" if c[0].startswith("`sweep_kernel<float, false") else
-               "batch" if c[0].startswith("`batch_kernel<float, false>") else None)
+               "batch" if c[0].startswith("`batch_kernel<float, false") else None)
         if key:
             out[key] = float(c[1]) + float(c[2])
     return out
