@@ -416,14 +416,15 @@ def adjoint_leg(C, torch):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     fwd, bwd = t1 - t0, t2 - t1
-    # one reverse step at 64^3 on its own (eager launches, HIP events)
-    lam64 = torch.zeros_like(q0)
-    C.cavity_nusselt_adjoint(g, C.Params(Ra=A.Ra), lam64, None)
+    # one reverse step at 64^3 on its own (eager launches, HIP events); the
+    # cotangent alternates between two buffers (a step cannot run in place)
+    lam64 = (torch.zeros_like(q0), torch.zeros_like(q0))
+    C.cavity_nusselt_adjoint(g, C.Params(Ra=A.Ra), lam64[0], None)
     aws64 = torch.empty(C.cavity_adjoint_workspace_bytes(g) // 8, dtype=torch.float64, device="cuda")
     C.cavity_timing_read()
     C.cavity_timing_enable(True)
-    for _ in range(20):
-        C.cavity_adjoint_step(g, C.Params(Ra=A.Ra), q0, lam64, lam64, aws64, None, None)
+    for r in range(20):
+        C.cavity_adjoint_step(g, C.Params(Ra=A.Ra), q0, lam64[r % 2], lam64[1 - r % 2], aws64, None, None)
     torch.cuda.synchronize()
     C.cavity_timing_enable(False)
     n_rev, rev_ms = C.cavity_timing_read().get("adjoint_step", (0, 0.0))
@@ -438,16 +439,16 @@ def adjoint_leg(C, torch):
     g2 = C.Grid.cube(256)
     q = torch.zeros(C.cavity_state_elems(g2), dtype=torch.float64, device="cuda")
     C.cavity_init(g2, C.Params(Ra=1e5), 2, 1e-3, q)
-    lam = torch.zeros_like(q)
-    C.cavity_nusselt_adjoint(g2, C.Params(Ra=1e5), lam, None)
+    lam = (torch.zeros_like(q), torch.zeros_like(q))
+    C.cavity_nusselt_adjoint(g2, C.Params(Ra=1e5), lam[0], None)
     aws = torch.empty(C.cavity_adjoint_workspace_bytes(g2) // 8, dtype=torch.float64, device="cuda")
-    for _ in range(2):
-        C.cavity_adjoint_step(g2, C.Params(Ra=1e5), q, lam, lam, aws, None, None)
+    for r in range(2):
+        C.cavity_adjoint_step(g2, C.Params(Ra=1e5), q, lam[r % 2], lam[1 - r % 2], aws, None, None)
     torch.cuda.synchronize()
     reps = 10
     t0 = time.perf_counter()
-    for _ in range(reps):
-        C.cavity_adjoint_step(g2, C.Params(Ra=1e5), q, lam, lam, aws, None, None)
+    for r in range(reps):
+        C.cavity_adjoint_step(g2, C.Params(Ra=1e5), q, lam[r % 2], lam[1 - r % 2], aws, None, None)
     torch.cuda.synchronize()
     us = 1e6 * (time.perf_counter() - t0) / reps
     cells = g2.ncell

@@ -281,7 +281,7 @@ int cavity_nusselt(const cav_grid* grid, const cav_params* prm, const void* q,
  * from checkpoints); every call must get the same params as the forward. */
 
 /* Bytes of the workspace cavity_adjoint_step needs (in doubles: 8, the
- * per-block partial sums, and 11 values per cell); 0 for an invalid grid or
+ * per-block partial sums, and 8 values per cell); 0 for an invalid grid or
  * a CAV_F32 grid. */
 size_t cavity_adjoint_workspace_bytes(const cav_grid* grid);
 
@@ -298,8 +298,9 @@ int cavity_nusselt_adjoint(const cav_grid* grid, const cav_params* prm, void* la
  * from, interior cells read), writes lam_out = dJ/dq^n on the interior cells
  * (its ghost cells are used as scratch and left unspecified) and ADDS this
  * step's terms into dj_dthot (device, nj*nk doubles, j fastest) and dj_dra
- * (device, 1 double); either may be NULL to skip it.  lam_out may equal
- * lam_in; neither may alias q_n.  ws: device, >=
+ * (device, 1 double); either may be NULL to skip it.  lam_out must not
+ * overlap lam_in (the gather reads lam_in at every cell's neighbours while
+ * it writes lam_out) or q_n; CAV_EINVAL when it equals either.  ws: device, >=
  * cavity_adjoint_workspace_bytes.  Three launches on `stream` (the record
  * pass, one block for the centre cell and the sums, the gather), no
  * allocation, no synchronisation.  CAV_EINVAL for a CAV_F32 grid. */

@@ -64,7 +64,8 @@ class NusseltAdjoint:
             states=torch.zeros((max(self.every - 1, 1), n), **f64),
             q=torch.zeros(n, **f64), tmp=torch.zeros(n, **f64),
             ws=torch.zeros(cavity_workspace_bytes(g) // 8, **f64),
-            lam=torch.zeros(n, **f64), dth=torch.zeros(g.nj * g.nk, **f64), dra=torch.zeros(1, **f64),
+            lam=(torch.zeros(n, **f64), torch.zeros(n, **f64)),
+            dth=torch.zeros(g.nj * g.nk, **f64), dra=torch.zeros(1, **f64),
             aws=torch.zeros(cavity_adjoint_workspace_bytes(g) // 8, **f64),
             theta=torch.zeros(g.nj * g.nk, **f64))
         self._g = None
@@ -87,12 +88,16 @@ class NusseltAdjoint:
     def _reverse(self):
         """Every launch of the backward pass, on the current stream: seed
         the cotangent of J, then per segment (last to first) recompute its
-        states from the checkpoint and run its reverse steps."""
+        states from the checkpoint and run its reverse steps.  The cotangent
+        alternates between two buffers (a reverse step reads its input at
+        every cell's neighbours, so it cannot write in place); after N steps
+        it is in buffer N mod 2."""
         B, g, prm = self._b, self.grid, self.prm
         lam, dth, dra = B["lam"], B["dth"], B["dra"]
         dth.zero_()
         dra.zero_()
-        cavity_nusselt_adjoint(g, prm, lam, dth)
+        cur = 0
+        cavity_nusselt_adjoint(g, prm, lam[cur], dth)
         for s in reversed(range(len(self.segs))):
             length = self.segs[s][1]
             states = [B["ckpt"][s]]
@@ -101,7 +106,8 @@ class NusseltAdjoint:
                 cavity_step_from(g, prm, states[-1], st)
                 states.append(st)
             for st in reversed(states):
-                cavity_adjoint_step(g, prm, st, lam, lam, B["aws"], dth, dra)
+                cavity_adjoint_step(g, prm, st, lam[cur], lam[1 - cur], B["aws"], dth, dra)
+                cur = 1 - cur
 
     def backward(self):
         """(dJ/dtheta (nj*nk), dJ/dRa (1), dJ/dq0 (flat state, zero ghosts))."""
@@ -123,7 +129,7 @@ class NusseltAdjoint:
                 self._reverse()
             self._g, self._g_ra = gr, self.prm.Ra
         g = self.grid
-        lam = B["lam"]
+        lam = B["lam"][self.nsteps % 2]
         dq0 = torch.zeros_like(lam)
         G = g.ng
         inner = (slice(None), slice(G, G + g.nk), slice(G, G + g.nj), slice(G, G + g.ni))

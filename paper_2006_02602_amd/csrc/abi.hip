@@ -808,6 +808,8 @@ int cavity_adjoint_step(const cav_grid* grid, const cav_params* prm, const void*
     if (grid->dtype != CAV_F64) return fail(CAV_EINVAL, "the adjoint is available for CAV_F64 only");
     if (!q_n || !lam_in || !lam_out || !ws) return fail(CAV_EINVAL, "q_n, lam_in, lam_out and ws must not be NULL");
     if (lam_out == q_n || lam_in == q_n) return fail(CAV_EINVAL, "the cotangents must not alias q_n");
+    if (lam_out == lam_in)
+        return fail(CAV_EINVAL, "lam_out must not alias lam_in (the gather reads lam_in at every cell's neighbours)");
     const Dims d = dims_of(grid);
     const size_t need = adjoint_ws_doubles(d) * sizeof(double);
     if (ws_bytes < need) return fail(CAV_ESIZE, "ws_bytes %zu < required %zu", ws_bytes, need);

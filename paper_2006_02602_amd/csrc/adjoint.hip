@@ -33,7 +33,7 @@ namespace cav {
 
 namespace {
 
-constexpr int NREC = 11;           // record values per cell
+constexpr int NREC = 8;            // record values per cell
 constexpr int ADJ_THREADS = 256;
 // Gather: rows (wavefronts) per block of the LDS tile kernel, and the
 // shortest k chunk it is used for (shorter chunks take the one-cell-per-
@@ -45,7 +45,7 @@ constexpr int ADJ_GTJ = CAV_ADJ_GATHER_TJ;
 #ifndef CAV_ADJ_TILE_MIN_KC
 #define CAV_ADJ_TILE_MIN_KC 8
 #endif
-enum { R_XX, R_XY, R_XZ, R_BP, R_UB, R_VB, R_WB, R_AU, R_AV, R_AW, R_AT };
+enum { R_XX, R_XY, R_XZ, R_BP, R_UB, R_VB, R_WB, R_DT };
 
 // Reverse of cell_residual for one cell, reduced to its record: given the
 // cotangents a[f] of R_f and b of dt, every star cotangent of the cell is
@@ -57,7 +57,8 @@ enum { R_XX, R_XY, R_XZ, R_BP, R_UB, R_VB, R_WB, R_AU, R_AV, R_AW, R_AT };
 //   T:      centre a_w + ctr alpha a_T; along each axis -+s a_T + alpha a_T/h^2
 // with Xi = eps4 a_p lambda_i/h_i, Bp = beta^2 a_p, (su, sv, sw) = V/(2h),
 // ctr = -2 sum 1/h^2, "-+" meaning - at +1 and + at -1.  rec receives
-// Xx, Xy, Xz, Bp, ub, vb, wb, a_u, a_v, a_w, a_T; nub, alb, dtvb are the
+// Xx, Xy, Xz, Bp, ub, vb, wb (the caller adds dt: a_u .. a_T are lambda_f dt,
+// rebuilt from lambda where they are needed); nub, alb, dtvb are the
 // cotangents of nu, alpha and the viscous step limit.  Non-smooth points
 // take one side: |u| has slope +1 at u = 0; beta^2 = max(|V|^2, floor)
 // follows |V|^2 only where strictly larger; dt follows the convective limit
@@ -133,10 +134,6 @@ __device__ __forceinline__ void reverse_record(const CoefR<double>& c, const Sta
     rec[R_UB] = ub;
     rec[R_VB] = vb;
     rec[R_WB] = wb;
-    rec[R_AU] = a[FU];
-    rec[R_AV] = a[FV];
-    rec[R_AW] = a[FW];
-    rec[R_AT] = a[FT];
 }
 
 __device__ __forceinline__ int centre_off(const Dims& d) { return cell_off(d, d.ni / 2, d.nj / 2, d.nk / 2); }
@@ -198,8 +195,9 @@ struct RecordEpi {
         }
         double v[NREC], nub, alb, dtvb;
         reverse_record(c, s, a, b, v, nub, alb, dtvb);
+        v[R_DT] = dt;
         const long long idx = i + (long long)d.ni * (j + (long long)d.nj * k);
-        // streaming stores: the record (88 B per cell) is read back only by
+        // streaming stores: the record (64 B per cell) is read back only by
         // the gather, after the whole pass
 #pragma unroll
         for (int m = 0; m < NREC; ++m) __builtin_nontemporal_store(v[m], &rec[(size_t)m * n + idx]);
@@ -295,18 +293,22 @@ struct GatherAcc {
     double Lp, Lu, Lv, Lw, Lt;
 };
 
-// lam*: lambda at e (the centre cell's p minus the rescale sum); own: e's
-// record (R_XX .. R_AT order).
+// lam: lambda at e (lam*, the cotangent e's record was seeded from, is
+// lambda except the centre cell's p, minus the rescale sum); own: e's record
+// (R_XX .. R_DT order).  e's seeds a_u .. a_T are lambda_f dt, the product
+// the record pass formed.
 __device__ __forceinline__ GatherAcc gather_init(const CoefR<double>& c, const double lam[NF], bool is_centre, double ps,
                                                  const double own[NREC])
 {
     const double ctr = -2.0 * ((c.ix2 + c.iy2) + c.iz2);
+    const double au = lam[FU] * own[R_DT], av = lam[FV] * own[R_DT], aw = lam[FW] * own[R_DT];
+    const double at = lam[FT] * own[R_DT];
     GatherAcc a;
     a.Lp = (is_centre ? lam[FP] - ps : lam[FP]) - 6.0 * ((own[R_XX] + own[R_XY]) + own[R_XZ]);
-    a.Lu = lam[FU] + (own[R_UB] + ctr * c.nu * own[R_AU]);
-    a.Lv = lam[FV] + (own[R_VB] + ctr * c.nu * own[R_AV]);
-    a.Lw = lam[FW] + (own[R_WB] + ctr * c.nu * own[R_AW]);
-    a.Lt = lam[FT] + (own[R_AW] + ctr * c.alpha * own[R_AT]);
+    a.Lu = lam[FU] + (own[R_UB] + ctr * c.nu * au);
+    a.Lv = lam[FV] + (own[R_VB] + ctr * c.nu * av);
+    a.Lw = lam[FW] + (own[R_WB] + ctr * c.nu * aw);
+    a.Lt = lam[FT] + (aw + ctr * c.alpha * at);
     return a;
 }
 
@@ -420,14 +422,16 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
 #pragma unroll
     for (int f = 0; f < NF; ++f) lm[f] = lam.f[f][o];
     GatherAcc a = gather_init(c, lm, o == centre_off(d), psum[0], own);
+    const double au = lm[FU] * own[R_DT], av = lm[FV] * own[R_DT], aw = lm[FW] * own[R_DT];
+    const double at = lm[FT] * own[R_DT];
 
     // The x neighbours are the cells of the adjacent lanes (a wavefront holds
-    // consecutive cells, i fastest): their record values and u arrive by
-    // cross-lane moves, loads remain only at the wavefront's edges.  Every
+    // consecutive cells, i fastest): their seeds, record values and u arrive
+    // by cross-lane moves, loads remain only at the wavefront's edges.  Every
     // lane moves before any branch; a lane whose neighbour is no cell of
     // this launch (it returned above) never uses the moved value.
     const int wl = threadIdx.x & 63;
-    const double sh_in[7] = {own[R_AU], own[R_AV], own[R_AW], own[R_AT], own[R_XX], own[R_BP], q.f[FU][o]};
+    const double sh_in[7] = {au, av, aw, at, own[R_XX], own[R_BP], q.f[FU][o]};
     double sh_lo[7], sh_hi[7];
 #pragma unroll
     for (int v = 0; v < 7; ++v) {
@@ -452,10 +456,12 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
                 b.s = S[6] * H;
                 return b;
             }
-            b.au = R(R_AU, m);
-            b.av = R(R_AV, m);
-            b.aw = R(R_AW, m);
-            b.at = R(R_AT, m);
+            const int on = o + sgn * pstride[ax];
+            const double dtm = R(R_DT, m);
+            b.au = lam.f[FU][on] * dtm;
+            b.av = lam.f[FV][on] * dtm;
+            b.aw = lam.f[FW][on] * dtm;
+            b.at = lam.f[FT][on] * dtm;
             b.X = R(R_XX + ax, m);
             b.Bp = R(R_BP, m);
             b.s = V[o + sgn * pstride[ax]] * H;
@@ -466,23 +472,27 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
         if (xx < nn - 1) hi = nb(+1);
         const double Xm2 = xx >= 2 ? R(R_XX + ax, idx - 2 * dstride[ax]) : 0.0;
         const double Xp2 = xx < nn - 2 ? R(R_XX + ax, idx + 2 * dstride[ax]) : 0.0;
-        const Nb me{own[R_AU], own[R_AV], own[R_AW], own[R_AT], own[R_XX + ax], own[R_BP], V[o] * H};
+        const Nb me{au, av, aw, at, own[R_XX + ax], own[R_BP], V[o] * H};
         gather_axis(a, c, ax, xx, nn, lo, hi, Xm2, Xp2, me,
                     (ax == 0 && dthot) ? &dthot[j + (long long)d.nj * k] : nullptr);
     }
     gather_store(a, out, o);
 }
 
-// One cell's record and velocity, as the k queue of the tile kernel holds it.
+// One cell's record, cotangent and velocity, as the k queue of the tile
+// kernel holds it.
 struct Column {
     double r[NREC];                    // the cell's record
+    double l[NF - 1];                  // lambda_u .. lambda_T (the seeds a_u .. a_T are lambda_f dt)
+    double lp;                         // lambda_p
     double u, v, w;                    // its velocity (for the neighbours' advection terms)
 };
 
 // The gather as a k-marching LDS tile: a block of 64 x TJ threads marches
 // its (i, j) columns through a k chunk.  Each plane, every thread puts the
-// nine values its in-plane neighbours need (a_u a_v a_w a_T, Bp, the x and
-// y dissipation terms, u, v) into the plane's LDS buffer, the block's
+// ten values its in-plane neighbours need (lambda_u .. lambda_T and dt, whose
+// products are the seeds, Bp, the x and y dissipation terms, u, v) into the
+// plane's LDS buffer, the block's
 // threads together add the tile's halo (two rows above and below, two
 // columns left and right, loaded one plane ahead into registers), and after
 // one barrier every cell reads its x and y neighbours from LDS; its z
@@ -492,17 +502,17 @@ struct Column {
 // the barrier of plane k+1 orders its writes after every read of plane
 // k-1's buffer.  Every thread runs every plane (no early exit), so the
 // barriers are uniform.
-enum { L_AU, L_AV, L_AW, L_AT, L_BP, L_XX, L_XY, L_U, L_V, NLV };
+enum { L_LU, L_LV, L_LW, L_LT, L_DT, L_BP, L_XX, L_XY, L_U, L_V, NLV };
 
 template <int TJ>
 struct GatherTile {
     static constexpr int THREADS = 64 * TJ;
     static constexpr int COLS = 68, ROWS = TJ + 4;            // two halo columns / rows on each side
     static constexpr int BUF = NLV * ROWS * COLS;             // doubles per plane buffer
-    // halo values per plane: rows -1 and TJ (7 values), rows -2 and TJ+1
-    // (the y dissipation term), columns -1 and 64 (7 values), columns -2
+    // halo values per plane: rows -1 and TJ (8 values), rows -2 and TJ+1
+    // (the y dissipation term), columns -1 and 64 (8 values), columns -2
     // and 65 (the x dissipation term)
-    static constexpr int NH = 2 * 7 * 64 + 2 * 64 + 2 * 7 * TJ + 2 * TJ;
+    static constexpr int NH = 2 * 8 * 64 + 2 * 64 + 2 * 8 * TJ + 2 * TJ;
     static constexpr int SLOTS = (NH + THREADS - 1) / THREADS;
     __device__ static int at(int v, int row, int col) { return (v * ROWS + row + 2) * COLS + col + 2; }
 };
@@ -536,23 +546,23 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
     // this thread's halo slots: source at k = 0, its stride per plane, and
     // the LDS slot (-1: outside the grid, nothing to load)
     const double* hsrc[T::SLOTS];
-    long long hstr[T::SLOTS];
+    int hstr[T::SLOTS];
     int hdst[T::SLOTS];
 #pragma unroll
     for (int s = 0; s < T::SLOTS; ++s) {
         int h = tid + s * T::THREADS;
         int v = -1, hr = 0, hc = 0;
-        if (h < 2 * 7 * 64) {                       // rows -1 and TJ
-            const int side = h / (7 * 64), r = h % (7 * 64);
-            const int vv[7] = {L_AU, L_AV, L_AW, L_AT, L_BP, L_XY, L_V};
+        if (h < 2 * 8 * 64) {                       // rows -1 and TJ
+            const int side = h / (8 * 64), r = h % (8 * 64);
+            const int vv[8] = {L_LU, L_LV, L_LW, L_LT, L_DT, L_BP, L_XY, L_V};
             v = vv[r / 64]; hc = r % 64; hr = side ? TJ : -1;
-        } else if ((h -= 2 * 7 * 64) < 2 * 64) {    // rows -2 and TJ+1
+        } else if ((h -= 2 * 8 * 64) < 2 * 64) {    // rows -2 and TJ+1
             v = L_XY; hc = h % 64; hr = h / 64 ? TJ + 1 : -2;
-        } else if ((h -= 2 * 64) < 2 * 7 * TJ) {    // columns -1 and 64
-            const int side = h / (7 * TJ), r = h % (7 * TJ);
-            const int vv[7] = {L_AU, L_AV, L_AW, L_AT, L_BP, L_XX, L_U};
+        } else if ((h -= 2 * 64) < 2 * 8 * TJ) {    // columns -1 and 64
+            const int side = h / (8 * TJ), r = h % (8 * TJ);
+            const int vv[8] = {L_LU, L_LV, L_LW, L_LT, L_DT, L_BP, L_XX, L_U};
             v = vv[r / TJ]; hr = r % TJ; hc = side ? 64 : -1;
-        } else if ((h -= 2 * 7 * TJ) < 2 * TJ) {    // columns -2 and 65
+        } else if ((h -= 2 * 8 * TJ) < 2 * TJ) {    // columns -2 and 65
             v = L_XX; hr = h % TJ; hc = h / TJ ? 65 : -2;
         }
         const int hi_ = tb.i0 + hc, hj = tb.j0 + hr;
@@ -561,10 +571,13 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
         hdst[s] = -1;
         if (v >= 0 && hi_ >= 0 && hi_ < d.ni && hj >= 0 && hj < d.nj) {
             const long long m = hi_ + (long long)d.ni * hj;
-            const int rv[L_U] = {R_AU, R_AV, R_AW, R_AT, R_BP, R_XX, R_XY};
-            if (v < L_U) {
-                hsrc[s] = rec + (size_t)rv[v] * n + m;
-                hstr[s] = plane;
+            if (v <= L_LT) {
+                hsrc[s] = lam.f[FU + (v - L_LU)] + cell_off(d, hi_, hj, 0);
+                hstr[s] = Z;
+            } else if (v < L_U) {
+                const int rv[L_U - L_DT] = {R_DT, R_BP, R_XX, R_XY};
+                hsrc[s] = rec + (size_t)rv[v - L_DT] * n + m;
+                hstr[s] = (int)plane;
             } else {
                 hsrc[s] = q.f[v == L_U ? FU : FV] + cell_off(d, hi_, hj, 0);
                 hstr[s] = Z;
@@ -579,7 +592,7 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
     auto load_halo = [&](int k, Halo& H) {
 #pragma unroll
         for (int s = 0; s < T::SLOTS; ++s)
-            if (hdst[s] >= 0) H.v[s] = hsrc[s][k * hstr[s]];
+            if (hdst[s] >= 0) H.v[s] = hsrc[s][(long long)k * hstr[s]];
     };
 
     auto R = [&](int v, long long m) { return rec[(size_t)v * n + m]; };
@@ -591,6 +604,10 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
         C.v = q.f[FV][ocol + k * Z];
         C.w = q.f[FW][ocol + k * Z];
     };
+    auto load_l = [&](int k, Column& C) {
+#pragma unroll
+        for (int f = FU; f <= FT; ++f) C.l[f - FU] = lam.f[f][ocol + k * Z];
+    };
     const int k0 = tb.k0, k1 = tb.k1, nk = d.nk;
     const double Hx = c.hx2, Hy = c.hy2, Hz = c.hz2;
     Nb prv{0, 0, 0, 0, 0, 0, 0};
@@ -598,29 +615,40 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
     if (k0 >= 2) xm2 = R(R_XZ, col + (k0 - 2) * plane);
     if (k0 >= 1) {
         const long long m = col + (k0 - 1) * plane;
-        prv = Nb{R(R_AU, m), R(R_AV, m), R(R_AW, m), R(R_AT, m), R(R_XZ, m), R(R_BP, m),
-                 q.f[FW][ocol + (k0 - 1) * Z] * Hz};
+        const int om = ocol + (k0 - 1) * Z;
+        const double dtm = R(R_DT, m);
+        prv = Nb{lam.f[FU][om] * dtm, lam.f[FV][om] * dtm, lam.f[FW][om] * dtm, lam.f[FT][om] * dtm, R(R_XZ, m),
+                 R(R_BP, m), q.f[FW][om] * Hz};
     }
     // Three register sets of planes (records and halo) rotate through the
     // roles k, k+1, k+2, so that no set is copied while its loads are in
-    // flight: each set is loaded three planes before it is the current one,
-    // at the same time as the neighbouring tiles load that plane's cells.
+    // flight: each set's record and velocity are loaded three planes before
+    // it is the current one, at the same time as the neighbouring tiles load
+    // that plane's cells; its lambda_u .. lambda_T two planes before, and its
+    // lambda_p one plane before (a value in flight holds its register, so
+    // the later loads keep fewer registers live; they are issued before the
+    // further plane's record, so waiting for them does not wait for it).
     Column C0, C1, C2;
     Halo H0, H1, H2;
+    C0.lp = lam.f[FP][ocol + k0 * Z];
+    load_l(k0, C0);
     load(k0, C0);
     load_halo(k0, H0);
-    if (k0 + 1 < nk) load(k0 + 1, C1);
+    if (k0 + 1 < nk) {
+        load_l(k0 + 1, C1);
+        load(k0 + 1, C1);
+    }
     if (k0 + 1 < k1) load_halo(k0 + 1, H1);
     if (k0 + 2 < nk) load(k0 + 2, C2);
     if (k0 + 2 < k1) load_halo(k0 + 2, H2);
 
     // plane k: cur = plane k, nxt = k+1, nn2 = k+2 (only its z dissipation
     // term is read); cur and H are reloaded with plane k+3 once used
-    auto body = [&](int k, Column& cur, const Column& nxt, const Column& nn2, Halo& H) __attribute__((always_inline)) {
+    auto body = [&](int k, Column& cur, Column& nxt, Column& nn2, Halo& H) __attribute__((always_inline)) {
         double* B = L + ((k - k0) & 1) * T::BUF;
         {
-            const double own[NLV] = {cur.r[R_AU], cur.r[R_AV], cur.r[R_AW], cur.r[R_AT], cur.r[R_BP],
-                                     cur.r[R_XX], cur.r[R_XY], cur.u, cur.v};
+            const double own[NLV] = {cur.l[0], cur.l[1], cur.l[2], cur.l[3], cur.r[R_DT],
+                                     cur.r[R_BP], cur.r[R_XX], cur.r[R_XY], cur.u, cur.v};
 #pragma unroll
             for (int v = 0; v < NLV; ++v) B[T::at(v, row, lane)] = own[v];
         }
@@ -631,26 +659,25 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
         __syncthreads();
 
         const int o = ocol + k * Z;
-        double lm[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) lm[f] = lam.f[f][o];
+        const double lm[NF] = {cur.lp, cur.l[0], cur.l[1], cur.l[2], cur.l[3]};
         GatherAcc a = gather_init(c, lm, o == centre, ps, cur.r);
-        auto nbx = [&](int dc) {
-            return Nb{B[T::at(L_AU, row, lane + dc)], B[T::at(L_AV, row, lane + dc)], B[T::at(L_AW, row, lane + dc)],
-                      B[T::at(L_AT, row, lane + dc)], B[T::at(L_XX, row, lane + dc)], B[T::at(L_BP, row, lane + dc)],
-                      B[T::at(L_U, row, lane + dc)] * Hx};
+        const double dt = cur.r[R_DT];
+        const double au = cur.l[0] * dt, av = cur.l[1] * dt, aw = cur.l[2] * dt, at = cur.l[3] * dt;
+        // the neighbour at (row, col) of the plane's buffer, with its x (or y)
+        // dissipation term X and velocity V
+        auto nbl = [&](int r, int cl, int X, int V, double H) {
+            const double dm = B[T::at(L_DT, r, cl)];
+            return Nb{B[T::at(L_LU, r, cl)] * dm, B[T::at(L_LV, r, cl)] * dm, B[T::at(L_LW, r, cl)] * dm,
+                      B[T::at(L_LT, r, cl)] * dm, B[T::at(X, r, cl)], B[T::at(L_BP, r, cl)], B[T::at(V, r, cl)] * H};
         };
-        auto nby = [&](int dr) {
-            return Nb{B[T::at(L_AU, row + dr, lane)], B[T::at(L_AV, row + dr, lane)], B[T::at(L_AW, row + dr, lane)],
-                      B[T::at(L_AT, row + dr, lane)], B[T::at(L_XY, row + dr, lane)], B[T::at(L_BP, row + dr, lane)],
-                      B[T::at(L_V, row + dr, lane)] * Hy};
-        };
+        auto nbx = [&](int dc) { return nbl(row, lane + dc, L_XX, L_U, Hx); };
+        auto nby = [&](int dr) { return nbl(row + dr, lane, L_XY, L_V, Hy); };
         {
             const Nb lo = i > 0 ? nbx(-1) : Nb{0, 0, 0, 0, 0, 0, 0};
             const Nb hi = i < d.ni - 1 ? nbx(+1) : Nb{0, 0, 0, 0, 0, 0, 0};
             const double Xm2 = i >= 2 ? B[T::at(L_XX, row, lane - 2)] : 0.0;
             const double Xp2 = i < d.ni - 2 ? B[T::at(L_XX, row, lane + 2)] : 0.0;
-            const Nb me{cur.r[R_AU], cur.r[R_AV], cur.r[R_AW], cur.r[R_AT], cur.r[R_XX], cur.r[R_BP], cur.u * Hx};
+            const Nb me{au, av, aw, at, cur.r[R_XX], cur.r[R_BP], cur.u * Hx};
             gather_axis(a, c, 0, i, d.ni, lo, hi, Xm2, Xp2, me,
                         (dthot && active) ? &dthot[j + (long long)d.nj * k] : nullptr);
         }
@@ -659,23 +686,28 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
             const Nb hi = j < d.nj - 1 ? nby(+1) : Nb{0, 0, 0, 0, 0, 0, 0};
             const double Xm2 = j >= 2 ? B[T::at(L_XY, row - 2, lane)] : 0.0;
             const double Xp2 = j < d.nj - 2 ? B[T::at(L_XY, row + 2, lane)] : 0.0;
-            const Nb me{cur.r[R_AU], cur.r[R_AV], cur.r[R_AW], cur.r[R_AT], cur.r[R_XY], cur.r[R_BP], cur.v * Hy};
+            const Nb me{au, av, aw, at, cur.r[R_XY], cur.r[R_BP], cur.v * Hy};
             gather_axis(a, c, 1, j, d.nj, lo, hi, Xm2, Xp2, me, nullptr);
         }
         {
-            const Nb hi = k < nk - 1 ? Nb{nxt.r[R_AU], nxt.r[R_AV], nxt.r[R_AW], nxt.r[R_AT], nxt.r[R_XZ],
-                                          nxt.r[R_BP], nxt.w * Hz}
+            const double dn = nxt.r[R_DT];
+            const Nb hi = k < nk - 1 ? Nb{nxt.l[0] * dn, nxt.l[1] * dn, nxt.l[2] * dn, nxt.l[3] * dn,
+                                          nxt.r[R_XZ], nxt.r[R_BP], nxt.w * Hz}
                                      : Nb{0, 0, 0, 0, 0, 0, 0};
             const double Xp2 = k < nk - 2 ? nn2.r[R_XZ] : 0.0;
-            const Nb me{cur.r[R_AU], cur.r[R_AV], cur.r[R_AW], cur.r[R_AT], cur.r[R_XZ], cur.r[R_BP], cur.w * Hz};
+            const Nb me{au, av, aw, at, cur.r[R_XZ], cur.r[R_BP], cur.w * Hz};
             gather_axis(a, c, 2, k, nk, k > 0 ? prv : Nb{0, 0, 0, 0, 0, 0, 0}, hi, k >= 2 ? xm2 : 0.0, Xp2, me,
                         nullptr);
         }
         if (active) gather_store<true>(a, out, o);
 
         xm2 = prv.X;
-        prv = Nb{cur.r[R_AU], cur.r[R_AV], cur.r[R_AW], cur.r[R_AT], cur.r[R_XZ], cur.r[R_BP], cur.w * Hz};
-        // plane k+3 is read from iteration k+1 on (as its k+2)
+        prv = Nb{au, av, aw, at, cur.r[R_XZ], cur.r[R_BP], cur.w * Hz};
+        // plane k+1's lambda_p (read in iteration k+1), plane k+2's lambda_u
+        // .. lambda_T (from iteration k+1 on, as its k+1), plane k+3's
+        // record (from iteration k+1 on, as its k+2)
+        if (k + 1 < k1) nxt.lp = lam.f[FP][o + Z];
+        if (k + 2 < nk && k + 1 < k1) load_l(k + 2, nn2);
         if (k + 3 < nk && k + 1 < k1) load(k + 3, cur);
     };
     for (int k = k0; k < k1; k += 3) {

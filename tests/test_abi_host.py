@@ -161,17 +161,21 @@ def test_adjoint_validation():
     need = C.cavity_adjoint_workspace_bytes(g64)
     # 8 head doubles + partials (rounded to 8: 5 per record-pass block, at
     # most tiles * max(1, nk/2) blocks, and 5 for the centre-cell block)
-    # + an 11-value record per cell
+    # + an 8-value record per cell
     tiles = 1 * 2
     nb = (tiles * max(1, 10 // 2) + 1) * 5
-    assert need == 8 * (8 + -(-nb // 8) * 8 + 11 * 16 * 12 * 10)
+    assert need == 8 * (8 + -(-nb // 8) * 8 + 8 * 16 * 12 * 10)
     assert C.cavity_adjoint_workspace_bytes(g32) == 0
     G, P = ctypes.byref(g64.c()), ctypes.byref(C.Params().c())
     a, b = FAKE, ctypes.c_void_p(FAKE.value + 4096)
-    assert L.cavity_adjoint_step(ctypes.byref(g32.c()), P, a, b, b, b, need, None, None, None) == C.CAV_EINVAL
-    assert L.cavity_adjoint_step(G, P, a, b, b, b, need - 8, None, None, None) == C.CAV_ESIZE
-    assert L.cavity_adjoint_step(G, P, a, a, b, b, need, None, None, None) == C.CAV_EINVAL
-    assert L.cavity_adjoint_step(G, P, None, b, b, b, need, None, None, None) == C.CAV_EINVAL
+    c, w = ctypes.c_void_p(FAKE.value + 8192), ctypes.c_void_p(FAKE.value + 12288)
+    assert L.cavity_adjoint_step(ctypes.byref(g32.c()), P, a, b, c, w, need, None, None, None) == C.CAV_EINVAL
+    assert L.cavity_adjoint_step(G, P, a, b, c, w, need - 8, None, None, None) == C.CAV_ESIZE
+    assert L.cavity_adjoint_step(G, P, a, a, c, w, need, None, None, None) == C.CAV_EINVAL
+    assert L.cavity_adjoint_step(G, P, None, b, c, w, need, None, None, None) == C.CAV_EINVAL
+    # in place: the gather reads lam_in at every cell's neighbours
+    assert L.cavity_adjoint_step(G, P, a, b, b, w, need, None, None, None) == C.CAV_EINVAL
+    assert "lam_in" in C.cavity_last_error()
     assert L.cavity_nusselt_adjoint(ctypes.byref(g32.c()), P, a, None, None) == C.CAV_EINVAL
     same = C.Params(t_hot=0.5, t_cold=0.5).c()
     assert L.cavity_nusselt_adjoint(G, ctypes.byref(same), a, None, None) == C.CAV_EINVAL
