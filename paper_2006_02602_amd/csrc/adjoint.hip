@@ -33,7 +33,8 @@ namespace cav {
 
 namespace {
 
-constexpr int NREC = 8;            // record values per cell
+constexpr int NREC = 8;            // record values per cell (full record)
+constexpr int NREC_C = 3;          // the compact record: ub, vb, wb
 constexpr int ADJ_THREADS = 256;
 // Gather: rows (wavefronts) per block of the LDS tile kernel, and the
 // shortest k chunk it is used for (shorter chunks take the one-cell-per-
@@ -45,7 +46,7 @@ constexpr int ADJ_GTJ = CAV_ADJ_GATHER_TJ;
 #ifndef CAV_ADJ_TILE_MIN_KC
 #define CAV_ADJ_TILE_MIN_KC 8
 #endif
-enum { R_XX, R_XY, R_XZ, R_BP, R_UB, R_VB, R_WB, R_DT };
+enum { R_UB, R_VB, R_WB, R_DT, R_XX, R_XY, R_XZ, R_BP };
 
 // Reverse of cell_residual for one cell, reduced to its record: given the
 // cotangents a[f] of R_f and b of dt, every star cotangent of the cell is
@@ -57,8 +58,9 @@ enum { R_XX, R_XY, R_XZ, R_BP, R_UB, R_VB, R_WB, R_DT };
 //   T:      centre a_w + ctr alpha a_T; along each axis -+s a_T + alpha a_T/h^2
 // with Xi = eps4 a_p lambda_i/h_i, Bp = beta^2 a_p, (su, sv, sw) = V/(2h),
 // ctr = -2 sum 1/h^2, "-+" meaning - at +1 and + at -1.  rec receives
-// Xx, Xy, Xz, Bp, ub, vb, wb (the caller adds dt: a_u .. a_T are lambda_f dt,
-// rebuilt from lambda where they are needed); nub, alb, dtvb are the
+// ub, vb, wb, Xx, Xy, Xz, Bp (the caller adds dt: a_u .. a_T are lambda_f dt,
+// rebuilt from lambda where they are needed; dt, the X and Bp depend only on
+// the cell's velocity and lambda*_p, see cell_d); nub, alb, dtvb are the
 // cotangents of nu, alpha and the viscous step limit.  Non-smooth points
 // take one side: |u| has slope +1 at u = 0; beta^2 = max(|V|^2, floor)
 // follows |V|^2 only where strictly larger; dt follows the convective limit
@@ -136,6 +138,32 @@ __device__ __forceinline__ void reverse_record(const CoefR<double>& c, const Sta
     rec[R_WB] = wb;
 }
 
+// The part of a cell's record that depends only on its velocity and
+// lambda*_p: dt, the dissipation terms Xx, Xy, Xz and Bp, by the formulas of
+// cell_residual and reverse_record, so the values are the same bits as the
+// record pass's.
+struct CellD {
+    double dt, X[3], Bp;
+};
+__device__ __forceinline__ CellD cell_d(const CoefR<double>& c, double u, double v, double w, double lps)
+{
+    const double u2 = u * u, v2 = v * v, w2 = w * w;
+    const double beta2 = fmax((u2 + v2) + w2, c.beta2_floor);
+    const double b4 = 4.0 * beta2;
+    const double lxn = (fabs(u) + sqrt_pos(u2 + b4)) * c.hx2;
+    const double lyn = (fabs(v) + sqrt_pos(v2 + b4)) * c.hy2;
+    const double lzn = (fabs(w) + sqrt_pos(w2 + b4)) * c.hz2;
+    CellD D;
+    D.dt = c.cfl * fmin(recip_pos((lxn + lyn) + lzn), c.dt_visc);
+    const double ap = lps * D.dt;
+    const double dissb = -c.eps4 * ap;
+    D.X[0] = -lxn * dissb;
+    D.X[1] = -lyn * dissb;
+    D.X[2] = -lzn * dissb;
+    D.Bp = beta2 * ap;
+    return D;
+}
+
 __device__ __forceinline__ int centre_off(const Dims& d) { return cell_off(d, d.ni / 2, d.nj / 2, d.nk / 2); }
 
 // ---- fixed-order sums of per-block partials ----
@@ -168,7 +196,10 @@ struct RaFactors {
 // reverse of the residual, the record stored at the cell's dense index, the
 // Ra term into acc[0] and lambda_p into acc[1] (the block's share of the
 // sum the centre cell's lambda* needs).  The centre cell itself is left to
-// a second launch (centre >= 0) once that sum is known.
+// a second launch (centre >= 0) once that sum is known.  COMPACT: store only
+// ub, vb, wb (the LDS tile gather forms the rest from the cell's velocity
+// and lambda, cell_d); else the full record.
+template <bool COMPACT>
 struct RecordEpi {
     CStateT<double> lam;
     double* rec;
@@ -197,18 +228,20 @@ struct RecordEpi {
         reverse_record(c, s, a, b, v, nub, alb, dtvb);
         v[R_DT] = dt;
         const long long idx = i + (long long)d.ni * (j + (long long)d.nj * k);
-        // streaming stores: the record (64 B per cell) is read back only by
-        // the gather, after the whole pass
+        // streaming stores: the record (24 or 64 B per cell) is read back
+        // only by the gather, after the whole pass
 #pragma unroll
-        for (int m = 0; m < NREC; ++m) __builtin_nontemporal_store(v[m], &rec[(size_t)m * n + idx]);
+        for (int m = 0; m < (COMPACT ? NREC_C : NREC); ++m)
+            __builtin_nontemporal_store(v[m], &rec[(size_t)m * n + idx]);
         acc[0] += (nub * rf.nu + alb * rf.alpha) + dtvb * rf.dtv;
     }
 };
 
 // Binds the grid to RecordEpi::cell (the tile passes no grid to its
 // epilogue).
+template <bool COMPACT>
 struct RecordEpiD {
-    RecordEpi e;
+    RecordEpi<COMPACT> e;
     Dims d;
     __device__ __forceinline__ void prepare(const Dims& dd, const CStateT<double>& q, const CoefR<double>& c)
     {
@@ -232,6 +265,7 @@ struct OwnCentre {
     __device__ __forceinline__ bool column(int, int) const { return true; }
 };
 
+template <bool COMPACT>
 __global__ __launch_bounds__(SW_TI * SW_TJ) void record_kernel(Dims d, Coef cd, SweepGeom g, RaFactors rf,
                                                                CStateT<double> q, CStateT<double> lam, double* rec,
                                                                double* partials)
@@ -239,9 +273,9 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void record_kernel(Dims d, Coef cd, 
     __shared__ SweepLds<double> L;
     const CoefR<double> c = coef_as<double>(cd);
     const TileBox tb = tile_box(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
-    RecordEpiD epi{{lam, rec, (long long)d.ni * d.nj * d.nk, rf, false, 0.0, -1}, d};
-    sweep_tile<double, true, OwnCentre<false>, RecordEpiD, 2>(d, c, tb, OwnCentre<false>{d.ni / 2, d.nj / 2, d.nk / 2},
-                                                              q, epi, partials, L);
+    RecordEpiD<COMPACT> epi{{lam, rec, (long long)d.ni * d.nj * d.nk, rf, false, 0.0, -1}, d};
+    sweep_tile<double, true, OwnCentre<false>, RecordEpiD<COMPACT>, 2>(
+        d, c, tb, OwnCentre<false>{d.ni / 2, d.nj / 2, d.nk / 2}, q, epi, partials, L);
 }
 
 // After the record pass, one block: the sum of lambda_p (the record blocks'
@@ -250,6 +284,7 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void record_kernel(Dims d, Coef cd, 
 // holding the centre, its plane only; partial slot nblocks); then, if dra
 // is not NULL, dra += the Ra partials of all nblocks + 1 slots in a fixed
 // order.
+template <bool COMPACT>
 __global__ __launch_bounds__(SW_TI * SW_TJ) void record_centre_kernel(Dims d, Coef cd, RaFactors rf, CStateT<double> q,
                                                                       CStateT<double> lam, double* psum, double* rec,
                                                                       double* partials, int nblocks, double* dra)
@@ -266,9 +301,9 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void record_centre_kernel(Dims d, Co
     tb.k0 = ck;
     tb.k1 = ck + 1;
     tb.pidx = nblocks;
-    RecordEpiD epi{{lam, rec, (long long)d.ni * d.nj * d.nk, rf, true, ps, -1}, d};
-    sweep_tile<double, true, OwnCentre<true>, RecordEpiD, 2>(d, c, tb, OwnCentre<true>{ci, cj, ck}, q, epi, partials,
-                                                             L);
+    RecordEpiD<COMPACT> epi{{lam, rec, (long long)d.ni * d.nj * d.nk, rf, true, ps, -1}, d};
+    sweep_tile<double, true, OwnCentre<true>, RecordEpiD<COMPACT>, 2>(d, c, tb, OwnCentre<true>{ci, cj, ck}, q, epi,
+                                                                      partials, L);
     if (dra) {
         __syncthreads();                  // this block's partial slot is written
         const double v = block_sum(partials, nblocks + 1, NF, red);
@@ -294,20 +329,20 @@ struct GatherAcc {
 };
 
 // lam: lambda at e (lam*, the cotangent e's record was seeded from, is
-// lambda except the centre cell's p, minus the rescale sum); own: e's record
-// (R_XX .. R_DT order).  e's seeds a_u .. a_T are lambda_f dt, the product
-// the record pass formed.
+// lambda except the centre cell's p, minus the rescale sum); ub, vb, wb and
+// D: e's record.  e's seeds a_u .. a_T are lambda_f dt, the product the
+// record pass formed.
 __device__ __forceinline__ GatherAcc gather_init(const CoefR<double>& c, const double lam[NF], bool is_centre, double ps,
-                                                 const double own[NREC])
+                                                 double ub, double vb, double wb, const CellD& D)
 {
     const double ctr = -2.0 * ((c.ix2 + c.iy2) + c.iz2);
-    const double au = lam[FU] * own[R_DT], av = lam[FV] * own[R_DT], aw = lam[FW] * own[R_DT];
-    const double at = lam[FT] * own[R_DT];
+    const double au = lam[FU] * D.dt, av = lam[FV] * D.dt, aw = lam[FW] * D.dt;
+    const double at = lam[FT] * D.dt;
     GatherAcc a;
-    a.Lp = (is_centre ? lam[FP] - ps : lam[FP]) - 6.0 * ((own[R_XX] + own[R_XY]) + own[R_XZ]);
-    a.Lu = lam[FU] + (own[R_UB] + ctr * c.nu * au);
-    a.Lv = lam[FV] + (own[R_VB] + ctr * c.nu * av);
-    a.Lw = lam[FW] + (own[R_WB] + ctr * c.nu * aw);
+    a.Lp = (is_centre ? lam[FP] - ps : lam[FP]) - 6.0 * ((D.X[0] + D.X[1]) + D.X[2]);
+    a.Lu = lam[FU] + (ub + ctr * c.nu * au);
+    a.Lv = lam[FV] + (vb + ctr * c.nu * av);
+    a.Lw = lam[FW] + (wb + ctr * c.nu * aw);
     a.Lt = lam[FT] + (aw + ctr * c.alpha * at);
     return a;
 }
@@ -421,7 +456,8 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
     double lm[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) lm[f] = lam.f[f][o];
-    GatherAcc a = gather_init(c, lm, o == centre_off(d), psum[0], own);
+    const CellD od{own[R_DT], {own[R_XX], own[R_XY], own[R_XZ]}, own[R_BP]};
+    GatherAcc a = gather_init(c, lm, o == centre_off(d), psum[0], own[R_UB], own[R_VB], own[R_WB], od);
     const double au = lm[FU] * own[R_DT], av = lm[FV] * own[R_DT], aw = lm[FW] * own[R_DT];
     const double at = lm[FT] * own[R_DT];
 
@@ -479,29 +515,32 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
     gather_store(a, out, o);
 }
 
-// One cell's record, cotangent and velocity, as the k queue of the tile
-// kernel holds it.
+// One cell's compact record, cotangent and velocity, and the rest of its
+// record formed from them, as the k queue of the tile kernel holds it.
 struct Column {
-    double r[NREC];                    // the cell's record
+    double ub, vb, wb;                 // the cell's compact record
     double l[NF - 1];                  // lambda_u .. lambda_T (the seeds a_u .. a_T are lambda_f dt)
     double lp;                         // lambda_p
-    double u, v, w;                    // its velocity (for the neighbours' advection terms)
+    double u, v, w;                    // its velocity
+    CellD D;                           // dt, the dissipation terms, Bp (cell_d)
 };
 
-// The gather as a k-marching LDS tile: a block of 64 x TJ threads marches
-// its (i, j) columns through a k chunk.  Each plane, every thread puts the
-// ten values its in-plane neighbours need (lambda_u .. lambda_T and dt, whose
-// products are the seeds, Bp, the x and y dissipation terms, u, v) into the
-// plane's LDS buffer, the block's
+// The gather as a k-marching LDS tile over the compact record: a block of
+// 64 x TJ threads marches its (i, j) columns through a k chunk.  Each cell's
+// dt, dissipation terms and Bp are formed once, from its velocity and
+// lambda_p (cell_d), when its plane enters the k queue two planes ahead.
+// Each plane, every thread puts the ten values its in-plane neighbours need
+// (lambda_u .. lambda_T and dt, whose products are the seeds, Bp, the x and
+// y dissipation terms, u, v) into the plane's LDS buffer, the block's
 // threads together add the tile's halo (two rows above and below, two
-// columns left and right, loaded one plane ahead into registers), and after
-// one barrier every cell reads its x and y neighbours from LDS; its z
-// neighbours (one and two planes away) are a register queue that loads each
-// plane once, two planes ahead.  So every record value is read from memory
-// once per tile, plus the halo.  Two LDS buffers alternate between planes:
-// the barrier of plane k+1 orders its writes after every read of plane
-// k-1's buffer.  Every thread runs every plane (no early exit), so the
-// barriers are uniform.
+// columns left and right; a halo thread loads a cell's velocity and
+// lambda_p and forms what the halo needs of them, or loads its lambda_u ..
+// lambda_T), and after one barrier every cell reads its x and y neighbours
+// from LDS; its z neighbours (one and two planes away) are the k queue.  So
+// every value is read from memory once per tile, plus the halo.  Two LDS
+// buffers alternate between planes: the barrier of plane k+1 orders its
+// writes after every read of plane k-1's buffer.  Every thread runs every
+// plane (no early exit), so the barriers are uniform.
 enum { L_LU, L_LV, L_LW, L_LT, L_DT, L_BP, L_XX, L_XY, L_U, L_V, NLV };
 
 template <int TJ>
@@ -509,10 +548,12 @@ struct GatherTile {
     static constexpr int THREADS = 64 * TJ;
     static constexpr int COLS = 68, ROWS = TJ + 4;            // two halo columns / rows on each side
     static constexpr int BUF = NLV * ROWS * COLS;             // doubles per plane buffer
-    // halo values per plane: rows -1 and TJ (8 values), rows -2 and TJ+1
-    // (the y dissipation term), columns -1 and 64 (8 values), columns -2
-    // and 65 (the x dissipation term)
-    static constexpr int NH = 2 * 8 * 64 + 2 * 64 + 2 * 8 * TJ + 2 * TJ;
+    static constexpr int VS = ROWS * COLS;                    // stride between the values of a cell
+    // halo slots per plane, four loads each: rows -1 and TJ (velocity +
+    // lambda_p, and lambda_u .. lambda_T), rows -2 and TJ+1 (velocity +
+    // lambda_p, for the y dissipation term), columns -1 and 64 (both kinds),
+    // columns -2 and 65 (velocity + lambda_p, for the x dissipation term)
+    static constexpr int NH = 2 * 2 * 64 + 2 * 64 + 2 * 2 * TJ + 2 * TJ;
     static constexpr int SLOTS = (NH + THREADS - 1) / THREADS;
     __device__ static int at(int v, int row, int col) { return (v * ROWS + row + 2) * COLS + col + 2; }
 };
@@ -526,6 +567,7 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
                                                                       double* __restrict__ dthot)
 {
     using T = GatherTile<TJ>;
+    static_assert(T::SLOTS == 1, "one halo slot per thread");
     __shared__ double L[2 * T::BUF];
     const CoefR<double> c = coef_as<double>(cd);
     const TileBox tb = tile_box<64, TJ>(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
@@ -542,126 +584,147 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
     const int Z = d.sz;
     const double ps = psum[0];
     const int centre = centre_off(d);
+    // lambda*_p of the cell at state offset o
+    auto lstar = [&](double lp, int o) { return o == centre ? lp - ps : lp; };
 
-    // this thread's halo slots: source at k = 0, its stride per plane, and
-    // the LDS slot (-1: outside the grid, nothing to load)
-    const double* hsrc[T::SLOTS];
-    int hstr[T::SLOTS];
-    int hdst[T::SLOTS];
-#pragma unroll
-    for (int s = 0; s < T::SLOTS; ++s) {
-        int h = tid + s * T::THREADS;
-        int v = -1, hr = 0, hc = 0;
-        if (h < 2 * 8 * 64) {                       // rows -1 and TJ
-            const int side = h / (8 * 64), r = h % (8 * 64);
-            const int vv[8] = {L_LU, L_LV, L_LW, L_LT, L_DT, L_BP, L_XY, L_V};
-            v = vv[r / 64]; hc = r % 64; hr = side ? TJ : -1;
-        } else if ((h -= 2 * 8 * 64) < 2 * 64) {    // rows -2 and TJ+1
-            v = L_XY; hc = h % 64; hr = h / 64 ? TJ + 1 : -2;
-        } else if ((h -= 2 * 64) < 2 * 8 * TJ) {    // columns -1 and 64
-            const int side = h / (8 * TJ), r = h % (8 * TJ);
-            const int vv[8] = {L_LU, L_LV, L_LW, L_LT, L_DT, L_BP, L_XX, L_U};
-            v = vv[r / TJ]; hr = r % TJ; hc = side ? 64 : -1;
-        } else if ((h -= 2 * 8 * TJ) < 2 * TJ) {    // columns -2 and 65
-            v = L_XX; hr = h % TJ; hc = h / TJ ? 65 : -2;
+    // this thread's halo slot: kind (-1: none or outside the grid; 0:
+    // velocity + lambda_p at rows/columns -1 and edge; 1: the same at -2 and
+    // edge+1, for the dissipation term only; 2: lambda_u .. lambda_T), the
+    // cell's state offset at k = 0, its LDS position (value 0), and whether
+    // it is a row (y) or a column (x) of the halo
+    int hkind = -1, hoff = 0, hpos = 0;
+    bool hrow = true;
+    {
+        int h = tid, hr = 0, hc = 0, kind = -1;
+        if (h < 2 * 2 * 64) {                       // rows -1 and TJ
+            kind = h / (2 * 64) ? 2 : 0;
+            const int r = h % (2 * 64);
+            hc = r % 64; hr = r / 64 ? TJ : -1;
+        } else if ((h -= 2 * 2 * 64) < 2 * 64) {    // rows -2 and TJ+1
+            kind = 1; hc = h % 64; hr = h / 64 ? TJ + 1 : -2;
+        } else if ((h -= 2 * 64) < 2 * 2 * TJ) {    // columns -1 and 64
+            kind = h / (2 * TJ) ? 2 : 0;
+            const int r = h % (2 * TJ);
+            hr = r % TJ; hc = r / TJ ? 64 : -1;
+            hrow = false;
+        } else if ((h -= 2 * 2 * TJ) < 2 * TJ) {    // columns -2 and 65
+            kind = 1; hr = h % TJ; hc = h / TJ ? 65 : -2;
+            hrow = false;
         }
         const int hi_ = tb.i0 + hc, hj = tb.j0 + hr;
-        hsrc[s] = nullptr;
-        hstr[s] = 0;
-        hdst[s] = -1;
-        if (v >= 0 && hi_ >= 0 && hi_ < d.ni && hj >= 0 && hj < d.nj) {
-            const long long m = hi_ + (long long)d.ni * hj;
-            if (v <= L_LT) {
-                hsrc[s] = lam.f[FU + (v - L_LU)] + cell_off(d, hi_, hj, 0);
-                hstr[s] = Z;
-            } else if (v < L_U) {
-                const int rv[L_U - L_DT] = {R_DT, R_BP, R_XX, R_XY};
-                hsrc[s] = rec + (size_t)rv[v - L_DT] * n + m;
-                hstr[s] = (int)plane;
-            } else {
-                hsrc[s] = q.f[v == L_U ? FU : FV] + cell_off(d, hi_, hj, 0);
-                hstr[s] = Z;
-            }
-            hdst[s] = T::at(v, hr, hc);
+        if (kind >= 0 && hi_ >= 0 && hi_ < d.ni && hj >= 0 && hj < d.nj) {
+            hkind = kind;
+            hoff = cell_off(d, hi_, hj, 0);
+            hpos = T::at(0, hr, hc);
         }
     }
-    // halo values of one plane
+    // the halo slot's four values of one plane
     struct Halo {
-        double v[T::SLOTS];
+        double v[4];
     };
     auto load_halo = [&](int k, Halo& H) {
+        const int o = hoff + k * Z;
+        if (hkind == 2) {
 #pragma unroll
-        for (int s = 0; s < T::SLOTS; ++s)
-            if (hdst[s] >= 0) H.v[s] = hsrc[s][(long long)k * hstr[s]];
+            for (int f = FU; f <= FT; ++f) H.v[f - FU] = lam.f[f][o];
+        } else if (hkind >= 0) {
+            H.v[0] = q.f[FU][o];
+            H.v[1] = q.f[FV][o];
+            H.v[2] = q.f[FW][o];
+            H.v[3] = lam.f[FP][o];
+        }
+    };
+    // what the slot puts into the plane's buffer B
+    auto store_halo = [&](int k, const Halo& H, double* B) {
+        if (hkind == 2) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) B[hpos + (L_LU + f) * T::VS] = H.v[f];
+        } else if (hkind >= 0) {
+            const CellD D = cell_d(c, H.v[0], H.v[1], H.v[2], lstar(H.v[3], hoff + k * Z));
+            B[hpos + (hrow ? L_XY : L_XX) * T::VS] = hrow ? D.X[1] : D.X[0];
+            if (hkind == 0) {
+                B[hpos + L_DT * T::VS] = D.dt;
+                B[hpos + L_BP * T::VS] = D.Bp;
+                B[hpos + (hrow ? L_V : L_U) * T::VS] = hrow ? H.v[1] : H.v[0];
+            }
+        }
     };
 
     auto R = [&](int v, long long m) { return rec[(size_t)v * n + m]; };
+    // the compact record, velocity and lambda_p of plane k
     auto load = [&](int k, Column& C) {
         const long long m = col + k * plane;
-#pragma unroll
-        for (int v = 0; v < NREC; ++v) C.r[v] = R(v, m);
-        C.u = q.f[FU][ocol + k * Z];
-        C.v = q.f[FV][ocol + k * Z];
-        C.w = q.f[FW][ocol + k * Z];
+        const int o = ocol + k * Z;
+        C.ub = R(R_UB, m);
+        C.vb = R(R_VB, m);
+        C.wb = R(R_WB, m);
+        C.u = q.f[FU][o];
+        C.v = q.f[FV][o];
+        C.w = q.f[FW][o];
+        C.lp = lam.f[FP][o];
     };
     auto load_l = [&](int k, Column& C) {
 #pragma unroll
         for (int f = FU; f <= FT; ++f) C.l[f - FU] = lam.f[f][ocol + k * Z];
     };
+    auto derive = [&](int k, Column& C) { C.D = cell_d(c, C.u, C.v, C.w, lstar(C.lp, ocol + k * Z)); };
     const int k0 = tb.k0, k1 = tb.k1, nk = d.nk;
     const double Hx = c.hx2, Hy = c.hy2, Hz = c.hz2;
     Nb prv{0, 0, 0, 0, 0, 0, 0};
     double xm2 = 0.0;
-    if (k0 >= 2) xm2 = R(R_XZ, col + (k0 - 2) * plane);
+    if (k0 >= 2) {
+        const int om = ocol + (k0 - 2) * Z;
+        xm2 = cell_d(c, q.f[FU][om], q.f[FV][om], q.f[FW][om], lstar(lam.f[FP][om], om)).X[2];
+    }
     if (k0 >= 1) {
-        const long long m = col + (k0 - 1) * plane;
         const int om = ocol + (k0 - 1) * Z;
-        const double dtm = R(R_DT, m);
-        prv = Nb{lam.f[FU][om] * dtm, lam.f[FV][om] * dtm, lam.f[FW][om] * dtm, lam.f[FT][om] * dtm, R(R_XZ, m),
-                 R(R_BP, m), q.f[FW][om] * Hz};
+        const CellD D = cell_d(c, q.f[FU][om], q.f[FV][om], q.f[FW][om], lstar(lam.f[FP][om], om));
+        prv = Nb{lam.f[FU][om] * D.dt, lam.f[FV][om] * D.dt, lam.f[FW][om] * D.dt, lam.f[FT][om] * D.dt, D.X[2],
+                 D.Bp, q.f[FW][om] * Hz};
     }
     // Three register sets of planes (records and halo) rotate through the
     // roles k, k+1, k+2, so that no set is copied while its loads are in
-    // flight: each set's record and velocity are loaded three planes before
-    // it is the current one, at the same time as the neighbouring tiles load
-    // that plane's cells; its lambda_u .. lambda_T two planes before, and its
-    // lambda_p one plane before (a value in flight holds its register, so
-    // the later loads keep fewer registers live; they are issued before the
-    // further plane's record, so waiting for them does not wait for it).
+    // flight: each set's compact record, velocity and lambda_p are loaded
+    // three planes before it is the current one, at the same time as the
+    // neighbouring tiles load that plane's cells, and formed into its dt, X
+    // and Bp two planes before; its lambda_u .. lambda_T are loaded two
+    // planes before (a value in flight holds its register; they are issued
+    // before the further plane's record, so waiting for them does not wait
+    // for it).
     Column C0, C1, C2;
     Halo H0, H1, H2;
-    C0.lp = lam.f[FP][ocol + k0 * Z];
-    load_l(k0, C0);
     load(k0, C0);
+    load_l(k0, C0);
     load_halo(k0, H0);
     if (k0 + 1 < nk) {
-        load_l(k0 + 1, C1);
         load(k0 + 1, C1);
+        load_l(k0 + 1, C1);
     }
     if (k0 + 1 < k1) load_halo(k0 + 1, H1);
     if (k0 + 2 < nk) load(k0 + 2, C2);
     if (k0 + 2 < k1) load_halo(k0 + 2, H2);
+    derive(k0, C0);
+    if (k0 + 1 < nk) derive(k0 + 1, C1);
 
-    // plane k: cur = plane k, nxt = k+1, nn2 = k+2 (only its z dissipation
-    // term is read); cur and H are reloaded with plane k+3 once used
+    // plane k: cur = plane k, nxt = k+1, nn2 = k+2 (its dt, X and Bp are
+    // formed here; only its z dissipation term is read); cur and H are
+    // reloaded with plane k+3 once used
     auto body = [&](int k, Column& cur, Column& nxt, Column& nn2, Halo& H) __attribute__((always_inline)) {
         double* B = L + ((k - k0) & 1) * T::BUF;
         {
-            const double own[NLV] = {cur.l[0], cur.l[1], cur.l[2], cur.l[3], cur.r[R_DT],
-                                     cur.r[R_BP], cur.r[R_XX], cur.r[R_XY], cur.u, cur.v};
+            const double own[NLV] = {cur.l[0], cur.l[1], cur.l[2], cur.l[3], cur.D.dt,
+                                     cur.D.Bp, cur.D.X[0], cur.D.X[1], cur.u, cur.v};
 #pragma unroll
             for (int v = 0; v < NLV; ++v) B[T::at(v, row, lane)] = own[v];
         }
-#pragma unroll
-        for (int s = 0; s < T::SLOTS; ++s)
-            if (hdst[s] >= 0) B[hdst[s]] = H.v[s];
+        store_halo(k, H, B);
         if (k + 3 < k1) load_halo(k + 3, H);
         __syncthreads();
 
         const int o = ocol + k * Z;
         const double lm[NF] = {cur.lp, cur.l[0], cur.l[1], cur.l[2], cur.l[3]};
-        GatherAcc a = gather_init(c, lm, o == centre, ps, cur.r);
-        const double dt = cur.r[R_DT];
+        GatherAcc a = gather_init(c, lm, o == centre, ps, cur.ub, cur.vb, cur.wb, cur.D);
+        const double dt = cur.D.dt;
         const double au = cur.l[0] * dt, av = cur.l[1] * dt, aw = cur.l[2] * dt, at = cur.l[3] * dt;
         // the neighbour at (row, col) of the plane's buffer, with its x (or y)
         // dissipation term X and velocity V
@@ -677,7 +740,7 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
             const Nb hi = i < d.ni - 1 ? nbx(+1) : Nb{0, 0, 0, 0, 0, 0, 0};
             const double Xm2 = i >= 2 ? B[T::at(L_XX, row, lane - 2)] : 0.0;
             const double Xp2 = i < d.ni - 2 ? B[T::at(L_XX, row, lane + 2)] : 0.0;
-            const Nb me{au, av, aw, at, cur.r[R_XX], cur.r[R_BP], cur.u * Hx};
+            const Nb me{au, av, aw, at, cur.D.X[0], cur.D.Bp, cur.u * Hx};
             gather_axis(a, c, 0, i, d.ni, lo, hi, Xm2, Xp2, me,
                         (dthot && active) ? &dthot[j + (long long)d.nj * k] : nullptr);
         }
@@ -686,27 +749,26 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
             const Nb hi = j < d.nj - 1 ? nby(+1) : Nb{0, 0, 0, 0, 0, 0, 0};
             const double Xm2 = j >= 2 ? B[T::at(L_XY, row - 2, lane)] : 0.0;
             const double Xp2 = j < d.nj - 2 ? B[T::at(L_XY, row + 2, lane)] : 0.0;
-            const Nb me{au, av, aw, at, cur.r[R_XY], cur.r[R_BP], cur.v * Hy};
+            const Nb me{au, av, aw, at, cur.D.X[1], cur.D.Bp, cur.v * Hy};
             gather_axis(a, c, 1, j, d.nj, lo, hi, Xm2, Xp2, me, nullptr);
         }
+        if (k + 2 < nk) derive(k + 2, nn2);
         {
-            const double dn = nxt.r[R_DT];
+            const double dn = nxt.D.dt;
             const Nb hi = k < nk - 1 ? Nb{nxt.l[0] * dn, nxt.l[1] * dn, nxt.l[2] * dn, nxt.l[3] * dn,
-                                          nxt.r[R_XZ], nxt.r[R_BP], nxt.w * Hz}
+                                          nxt.D.X[2], nxt.D.Bp, nxt.w * Hz}
                                      : Nb{0, 0, 0, 0, 0, 0, 0};
-            const double Xp2 = k < nk - 2 ? nn2.r[R_XZ] : 0.0;
-            const Nb me{au, av, aw, at, cur.r[R_XZ], cur.r[R_BP], cur.w * Hz};
+            const double Xp2 = k < nk - 2 ? nn2.D.X[2] : 0.0;
+            const Nb me{au, av, aw, at, cur.D.X[2], cur.D.Bp, cur.w * Hz};
             gather_axis(a, c, 2, k, nk, k > 0 ? prv : Nb{0, 0, 0, 0, 0, 0, 0}, hi, k >= 2 ? xm2 : 0.0, Xp2, me,
                         nullptr);
         }
         if (active) gather_store<true>(a, out, o);
 
         xm2 = prv.X;
-        prv = Nb{au, av, aw, at, cur.r[R_XZ], cur.r[R_BP], cur.w * Hz};
-        // plane k+1's lambda_p (read in iteration k+1), plane k+2's lambda_u
-        // .. lambda_T (from iteration k+1 on, as its k+1), plane k+3's
-        // record (from iteration k+1 on, as its k+2)
-        if (k + 1 < k1) nxt.lp = lam.f[FP][o + Z];
+        prv = Nb{au, av, aw, at, cur.D.X[2], cur.D.Bp, cur.w * Hz};
+        // plane k+2's lambda_u .. lambda_T (from iteration k+1 on, as its
+        // k+1), plane k+3's record (from iteration k+1 on, as its k+2)
         if (k + 2 < nk && k + 1 < k1) load_l(k + 2, nn2);
         if (k + 3 < nk && k + 1 < k1) load(k + 3, cur);
     };
@@ -769,13 +831,22 @@ hipError_t launch_adjoint_step(const Dims& d, const Coef& c, const SweepGeom& g,
     rf.nu = -c.nu / (2.0 * Ra);
     rf.alpha = -c.alpha / (2.0 * Ra);
     rf.dtv = c.dt_visc / (2.0 * Ra);
+    // the LDS tile gather reads the compact record, the one-cell gather the
+    // full one
+    const bool tile = gg.kc >= CAV_ADJ_TILE_MIN_KC;
     // every record but the centre cell's; each block's sum of lambda_p
-    record_kernel<<<g.nblocks, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, g, rf, q, lam_in, rec, part);
+    if (tile) record_kernel<true><<<g.nblocks, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, g, rf, q, lam_in, rec, part);
+    else record_kernel<false><<<g.nblocks, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, g, rf, q, lam_in, rec, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // the sum of lambda_p, the centre cell's record, the Ra cotangent
-    record_centre_kernel<<<1, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, rf, q, lam_in, psum, rec, part, g.nblocks, dra);
+    if (tile)
+        record_centre_kernel<true><<<1, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, rf, q, lam_in, psum, rec, part, g.nblocks,
+                                                                    dra);
+    else
+        record_centre_kernel<false><<<1, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, rf, q, lam_in, psum, rec, part,
+                                                                     g.nblocks, dra);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (gg.kc >= CAV_ADJ_TILE_MIN_KC) {
+    if (tile) {
         adjoint_gather_tile_kernel<ADJ_GTJ><<<gg.nblocks, dim3(64, ADJ_GTJ), 0, s>>>(d, c, gg, q, lam_in, psum, rec,
                                                                                  lam_out, dthot);
     } else {

@@ -329,7 +329,7 @@ def test_reverse_step_full_size_tile_edges(C):
         assert abs(got - fd) <= 1e-6 * max(abs(fd), 1e-3), (f, i, j, k, got, fd)
 
 
-def test_checkpoint_interval_and_in_place_change_nothing(C):
+def test_checkpoint_interval_changes_nothing(C):
     say("adjoint checkpoint invariance")
     n, Ra, steps = (16, 12, 10), 1e5, 24
     theta = theta_of(n, 2)
