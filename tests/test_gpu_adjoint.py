@@ -15,7 +15,8 @@ differentiates with respect to.
     one forward step (both gather kernels, 1e-11 of the inner products'
     absolute sums), and at 256^3 on the gather tile's edges against central
     differences of the forward step (1e-6);
-  * checkpoint interval and in-place cotangents change nothing (bit-exact);
+  * the checkpoint interval changes nothing (bit-exact), and a reverse step
+    in place is refused;
   * the torch.autograd wrapper returns the same gradient.
 """
 import sys
