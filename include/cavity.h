@@ -301,8 +301,8 @@ int cavity_nusselt_adjoint(const cav_grid* grid, const cav_params* prm, void* la
  * (device, 1 double); either may be NULL to skip it.  lam_out must not
  * overlap lam_in (the gather reads lam_in at every cell's neighbours while
  * it writes lam_out) or q_n; CAV_EINVAL when it equals either.  ws: device, >=
- * cavity_adjoint_workspace_bytes.  Three launches on `stream` (the record
- * pass, one block for the centre cell and the sums, the gather), no
+ * cavity_adjoint_workspace_bytes.  Two launches on `stream` (the record
+ * pass; the gather, which also forms the rescale sum and the Ra sum), no
  * allocation, no synchronisation.  CAV_EINVAL for a CAV_F32 grid. */
 int cavity_adjoint_step(const cav_grid* grid, const cav_params* prm,
                         const void* q_n, const void* lam_in, void* lam_out,

@@ -166,25 +166,19 @@ __device__ __forceinline__ CellD cell_d(const CoefR<double>& c, double u, double
 
 __device__ __forceinline__ int centre_off(const Dims& d) { return cell_off(d, d.ni / 2, d.nj / 2, d.nk / 2); }
 
-// ---- fixed-order sums of per-block partials ----
-// Sum of part[b * stride] for b < n: thread t < ADJ_THREADS adds b = t,
-// t + ADJ_THREADS, ..., then a fixed tree.  Every thread of the block calls
-// it (it holds barriers) and gets the sum.
-__device__ double block_sum(const double* __restrict__ part, int n, int stride, double* red)
+// ---- fixed-order sum of per-block partials ----
+// Sum of part[b * stride] for b < n, by one whole wavefront: lane l adds
+// b = l, l + 64, ... in order, then a butterfly over the lanes.  IEEE
+// addition commutes, so every lane gets the same bits, and so does every
+// wavefront that calls it.  All 64 lanes must be active.
+__device__ double wave_sum(const double* __restrict__ part, int n, int stride)
 {
-    const int t = threadIdx.x + blockDim.x * threadIdx.y;
+    const int l = threadIdx.x & 63;
     double acc = 0.0;
-    if (t < ADJ_THREADS)
-        for (int b = t; b < n; b += ADJ_THREADS) acc += part[(size_t)b * stride];
-    if (t < ADJ_THREADS) red[t] = acc;
-    __syncthreads();
-    for (int w = ADJ_THREADS / 2; w > 0; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
-    }
-    const double v = red[0];
-    __syncthreads();                      // red may be reused
-    return v;
+    for (int b = l; b < n; b += 64) acc += part[(size_t)b * stride];
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 64);
+    return acc;
 }
 
 // ---- 2. record pass ----
@@ -192,25 +186,27 @@ struct RaFactors {
     double nu, alpha, dtv;        // d(nu)/dRa, d(alpha)/dRa, d(dt_visc)/dRa
 };
 
-// What the k-marching tile does with each cell: seeds from lambda*, the
+// What the k-marching tile does with each cell: seeds from lambda, the
 // reverse of the residual, the record stored at the cell's dense index, the
 // Ra term into acc[0] and lambda_p into acc[1] (the block's share of the
-// sum the centre cell's lambda* needs).  The centre cell itself is left to
-// a second launch (centre >= 0) once that sum is known.  COMPACT: store only
-// ub, vb, wb (the LDS tile gather forms the rest from the cell's velocity
-// and lambda, cell_d); else the full record.
+// sum S of lambda_p).  The transpose of the centre rescale seeds the centre
+// cell with lambda*_p = lambda_p - S instead, and S is known only after
+// the pass; the record and the Ra term are linear in the seeds, so the
+// centre cell also stores ub, vb, wb and the Ra term of a unit p seed
+// (a_p = dt, b = R_p) at cx[0..3], and the gather subtracts S times them.
+// COMPACT: store only ub, vb, wb (the LDS tile gather forms the rest from
+// the cell's velocity and lambda, cell_d); else the full record.
 template <bool COMPACT>
 struct RecordEpi {
     CStateT<double> lam;
     double* rec;
     long long n;
     RaFactors rf;
-    bool fix;                  // the centre-cell launch
-    double ps;                 // the sum of lambda_p (the centre-cell launch)
+    double* cx;
     int centre;
     __device__ __forceinline__ void prepare(const Dims& d, const CStateT<double>&, const CoefR<double>&)
     {
-        centre = fix ? centre_off(d) : -1;
+        centre = centre_off(d);
     }
     __device__ __forceinline__ void cell(const CoefR<double>& c, const Star<double>& s, const double R[NF], double dt,
                                          int o, int i, int j, int k, double acc[NF], const Dims& d)
@@ -219,9 +215,8 @@ struct RecordEpi {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const double l = lam.f[f][o];
-            const double ls = (f == FP && o == centre) ? l - ps : l;
-            a[f] = ls * dt;
-            b = fma(ls, R[f], b);
+            a[f] = l * dt;
+            b = fma(l, R[f], b);
             if (f == FP) acc[1] += l;
         }
         double v[NREC], nub, alb, dtvb;
@@ -234,6 +229,15 @@ struct RecordEpi {
         for (int m = 0; m < (COMPACT ? NREC_C : NREC); ++m)
             __builtin_nontemporal_store(v[m], &rec[(size_t)m * n + idx]);
         acc[0] += (nub * rf.nu + alb * rf.alpha) + dtvb * rf.dtv;
+        if (o == centre) {
+            const double ae[NF] = {dt, 0.0, 0.0, 0.0, 0.0};
+            double ve[NREC], nue, ale, dte;
+            reverse_record(c, s, ae, R[FP], ve, nue, ale, dte);
+            cx[0] = ve[R_UB];
+            cx[1] = ve[R_VB];
+            cx[2] = ve[R_WB];
+            cx[3] = (nue * rf.nu + ale * rf.alpha) + dte * rf.dtv;
+        }
     }
 };
 
@@ -254,62 +258,33 @@ struct RecordEpiD {
     }
 };
 
-// Every cell but (ci, cj, ck), or only that cell.
-template <bool ONLY>
-struct OwnCentre {
-    int ci, cj, ck;
-    __device__ __forceinline__ bool operator()(int i, int j, int k) const
-    {
-        return (i == ci && j == cj && k == ck) == ONLY;
-    }
-    __device__ __forceinline__ bool column(int, int) const { return true; }
-};
-
 template <bool COMPACT>
 __global__ __launch_bounds__(SW_TI * SW_TJ) void record_kernel(Dims d, Coef cd, SweepGeom g, RaFactors rf,
                                                                CStateT<double> q, CStateT<double> lam, double* rec,
-                                                               double* partials)
+                                                               double* partials, double* cx)
 {
     __shared__ SweepLds<double> L;
     const CoefR<double> c = coef_as<double>(cd);
     const TileBox tb = tile_box(d, g.tiles_i, g.tiles_j, g.kc, xcd_block(blockIdx.x, g.nblocks));
-    RecordEpiD<COMPACT> epi{{lam, rec, (long long)d.ni * d.nj * d.nk, rf, false, 0.0, -1}, d};
-    sweep_tile<double, true, OwnCentre<false>, RecordEpiD<COMPACT>, 2>(
-        d, c, tb, OwnCentre<false>{d.ni / 2, d.nj / 2, d.nk / 2}, q, epi, partials, L);
+    RecordEpiD<COMPACT> epi{{lam, rec, (long long)d.ni * d.nj * d.nk, rf, cx, -1}, d};
+    sweep_tile<double, true, OwnAll, RecordEpiD<COMPACT>, 2>(d, c, tb, OwnAll{}, q, epi, partials, L);
 }
 
-// After the record pass, one block: the sum of lambda_p (the record blocks'
-// sums in a fixed order, then the centre cell's), stored for the gather;
-// the centre cell's record with lambda*_p = lambda_p - that sum (the tile
-// holding the centre, its plane only; partial slot nblocks); then, if dra
-// is not NULL, dra += the Ra partials of all nblocks + 1 slots in a fixed
-// order.
-template <bool COMPACT>
-__global__ __launch_bounds__(SW_TI * SW_TJ) void record_centre_kernel(Dims d, Coef cd, RaFactors rf, CStateT<double> q,
-                                                                      CStateT<double> lam, double* psum, double* rec,
-                                                                      double* partials, int nblocks, double* dra)
-{
-    __shared__ SweepLds<double> L;
-    __shared__ double red[ADJ_THREADS];
-    const CoefR<double> c = coef_as<double>(cd);
-    const int ci = d.ni / 2, cj = d.nj / 2, ck = d.nk / 2;
-    const double ps = block_sum(partials + 1, nblocks, NF, red) + lam.f[FP][cell_off(d, ci, cj, ck)];
-    if (threadIdx.x == 0 && threadIdx.y == 0) psum[0] = ps;
-    TileBox tb;
-    tb.i0 = ci / SW_TI * SW_TI;
-    tb.j0 = cj / SW_TJ * SW_TJ;
-    tb.k0 = ck;
-    tb.k1 = ck + 1;
-    tb.pidx = nblocks;
-    RecordEpiD<COMPACT> epi{{lam, rec, (long long)d.ni * d.nj * d.nk, rf, true, ps, -1}, d};
-    sweep_tile<double, true, OwnCentre<true>, RecordEpiD<COMPACT>, 2>(d, c, tb, OwnCentre<true>{ci, cj, ck}, q, epi,
-                                                                      partials, L);
-    if (dra) {
-        __syncthreads();                  // this block's partial slot is written
-        const double v = block_sum(partials, nblocks + 1, NF, red);
-        if (threadIdx.x == 0 && threadIdx.y == 0) dra[0] += v;
+// The rescale sum S (every record block's lambda_p partial) and, if dra is
+// not NULL, dra += the Ra partials of every record block minus S times the
+// unit p seed's Ra term at the centre (cx[3]): one whole wavefront, the one
+// holding the centre cell, so it happens once per reverse step.
+struct CentreTerms {
+    const double* part;
+    int nblocks;
+    const double* cx;
+    __device__ __forceinline__ double sum() const { return wave_sum(part + 1, nblocks, NF); }
+    __device__ __forceinline__ void add_ra(double S, double* dra) const
+    {
+        const double v = wave_sum(part, nblocks, NF) - S * cx[3];
+        if ((threadIdx.x & 63) == 0) dra[0] += v;
     }
-}
+};
 
 // What the gather needs from a neighbour m one cell away along an axis:
 // the four velocity/temperature seeds, that axis's dissipation term and Bp,
@@ -431,10 +406,10 @@ __device__ __forceinline__ void gather_store(const GatherAcc& a, StateT<double>&
 // XCD's L2.  (Its z neighbours' records, a slab-plane away, mostly are not:
 // the blocks in flight on an XCD span more than its L2 holds.)
 __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coef cd, CStateT<double> q,
-                                                                     CStateT<double> lam,
-                                                                     const double* __restrict__ psum,
+                                                                     CStateT<double> lam, CentreTerms ct,
                                                                      const double* __restrict__ rec,
-                                                                     StateT<double> out, double* __restrict__ dthot)
+                                                                     StateT<double> out, double* __restrict__ dthot,
+                                                                     double* __restrict__ dra)
 {
     const CoefR<double> c = coef_as<double>(cd);
     const long long n = (long long)d.ni * d.nj * d.nk;
@@ -442,24 +417,48 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
     const int j0 = (int)((long long)x * d.nj / 8);
     const int w = (int)((long long)(x + 1) * d.nj / 8) - j0;
     const long long cl = (long long)(blockIdx.x >> 3) * ADJ_THREADS + threadIdx.x;
-    if (cl >= (long long)d.ni * w * d.nk) return;
-    const int i = (int)(cl % d.ni);
-    const long long r = cl / d.ni;
+    const bool in = cl < (long long)d.ni * w * d.nk;
+    const long long cc = in ? cl : 0;
+    const int i = (int)(cc % d.ni);
+    const long long r = cc / d.ni;
     const int j = j0 + (int)(r % w), k = (int)(r / w);
+    const int ci = d.ni / 2, cj = d.nj / 2, ck = d.nk / 2;
+    // The rescale sum S, in every wavefront holding a cell within two of the
+    // centre (the cells that read the centre's seeds); the wavefront holding
+    // the centre adds the Ra term.  Every lane is still active here.
+    double S = 0.0;
+    if (__any(in && abs(i - ci) <= 2 && abs(j - cj) <= 2 && abs(k - ck) <= 2)) {
+        S = ct.sum();
+        if (dra && __any(in && i == ci && j == cj && k == ck)) ct.add_ra(S, dra);
+    }
+    if (!in) return;
     const long long idx = i + (long long)d.ni * (j + (long long)d.nj * k);
     const int o = cell_off(d, i, j, k);
+    const int centre = centre_off(d);
     auto R = [&](int v, long long m) { return rec[(size_t)v * n + m]; };
+    // dt, X and Bp of the cell at state offset om, dense index m: its record,
+    // or at the centre formed from lambda*_p (its record holds lambda_p's)
+    auto dxb = [&](long long m, int om) {
+        if (om == centre) return cell_d(c, q.f[FU][om], q.f[FV][om], q.f[FW][om], lam.f[FP][om] - S);
+        return CellD{R(R_DT, m), {R(R_XX, m), R(R_XY, m), R(R_XZ, m)}, R(R_BP, m)};
+    };
 
-    double own[NREC];
+    double own[NREC_C];
 #pragma unroll
-    for (int v = 0; v < NREC; ++v) own[v] = R(v, idx);
+    for (int v = 0; v < NREC_C; ++v) own[v] = R(v, idx);
     double lm[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) lm[f] = lam.f[f][o];
-    const CellD od{own[R_DT], {own[R_XX], own[R_XY], own[R_XZ]}, own[R_BP]};
-    GatherAcc a = gather_init(c, lm, o == centre_off(d), psum[0], own[R_UB], own[R_VB], own[R_WB], od);
-    const double au = lm[FU] * own[R_DT], av = lm[FV] * own[R_DT], aw = lm[FW] * own[R_DT];
-    const double at = lm[FT] * own[R_DT];
+    const CellD od = dxb(idx, o);
+    const bool isc = o == centre;
+    if (isc) {
+        own[R_UB] -= S * ct.cx[0];
+        own[R_VB] -= S * ct.cx[1];
+        own[R_WB] -= S * ct.cx[2];
+    }
+    GatherAcc a = gather_init(c, lm, isc, S, own[R_UB], own[R_VB], own[R_WB], od);
+    const double au = lm[FU] * od.dt, av = lm[FV] * od.dt, aw = lm[FW] * od.dt;
+    const double at = lm[FT] * od.dt;
 
     // The x neighbours are the cells of the adjacent lanes (a wavefront holds
     // consecutive cells, i fastest): their seeds, record values and u arrive
@@ -467,7 +466,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
     // lane moves before any branch; a lane whose neighbour is no cell of
     // this launch (it returned above) never uses the moved value.
     const int wl = threadIdx.x & 63;
-    const double sh_in[7] = {au, av, aw, at, own[R_XX], own[R_BP], q.f[FU][o]};
+    const double sh_in[7] = {au, av, aw, at, od.X[0], od.Bp, q.f[FU][o]};
     double sh_lo[7], sh_hi[7];
 #pragma unroll
     for (int v = 0; v < 7; ++v) {
@@ -493,22 +492,22 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
                 return b;
             }
             const int on = o + sgn * pstride[ax];
-            const double dtm = R(R_DT, m);
-            b.au = lam.f[FU][on] * dtm;
-            b.av = lam.f[FV][on] * dtm;
-            b.aw = lam.f[FW][on] * dtm;
-            b.at = lam.f[FT][on] * dtm;
-            b.X = R(R_XX + ax, m);
-            b.Bp = R(R_BP, m);
-            b.s = V[o + sgn * pstride[ax]] * H;
+            const CellD D = dxb(m, on);
+            b.au = lam.f[FU][on] * D.dt;
+            b.av = lam.f[FV][on] * D.dt;
+            b.aw = lam.f[FW][on] * D.dt;
+            b.at = lam.f[FT][on] * D.dt;
+            b.X = D.X[ax];
+            b.Bp = D.Bp;
+            b.s = V[on] * H;
             return b;
         };
         Nb lo{0, 0, 0, 0, 0, 0, 0}, hi{0, 0, 0, 0, 0, 0, 0};
         if (xx > 0) lo = nb(-1);
         if (xx < nn - 1) hi = nb(+1);
-        const double Xm2 = xx >= 2 ? R(R_XX + ax, idx - 2 * dstride[ax]) : 0.0;
-        const double Xp2 = xx < nn - 2 ? R(R_XX + ax, idx + 2 * dstride[ax]) : 0.0;
-        const Nb me{au, av, aw, at, own[R_XX + ax], own[R_BP], V[o] * H};
+        const double Xm2 = xx >= 2 ? dxb(idx - 2 * dstride[ax], o - 2 * pstride[ax]).X[ax] : 0.0;
+        const double Xp2 = xx < nn - 2 ? dxb(idx + 2 * dstride[ax], o + 2 * pstride[ax]).X[ax] : 0.0;
+        const Nb me{au, av, aw, at, od.X[ax], od.Bp, V[o] * H};
         gather_axis(a, c, ax, xx, nn, lo, hi, Xm2, Xp2, me,
                     (ax == 0 && dthot) ? &dthot[j + (long long)d.nj * k] : nullptr);
     }
@@ -561,10 +560,11 @@ struct GatherTile {
 template <int TJ>
 __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Coef cd, SweepGeom g,
                                                                       CStateT<double> q, CStateT<double> lam,
-                                                                      const double* __restrict__ psum,
+                                                                      CentreTerms ct,
                                                                       const double* __restrict__ rec,
                                                                       StateT<double> out,
-                                                                      double* __restrict__ dthot)
+                                                                      double* __restrict__ dthot,
+                                                                      double* __restrict__ dra)
 {
     using T = GatherTile<TJ>;
     static_assert(T::SLOTS == 1, "one halo slot per thread");
@@ -582,8 +582,17 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
     const long long col = ic + (long long)d.ni * jc;
     const int ocol = cell_off(d, ic, jc, 0);
     const int Z = d.sz;
-    const double ps = psum[0];
     const int centre = centre_off(d);
+    const int ci = d.ni / 2, cj = d.nj / 2, ck = d.nk / 2;
+    // The rescale sum S, in blocks whose cells or halo reach the centre
+    // (every wavefront forms it); the wavefront holding the centre adds the
+    // Ra term.
+    double ps = 0.0;
+    if (ci >= tb.i0 - 2 && ci < tb.i0 + 66 && cj >= tb.j0 - 2 && cj < tb.j0 + TJ + 2 && ck >= tb.k0 - 2 &&
+        ck < tb.k1 + 2) {
+        ps = ct.sum();
+        if (dra && ci >= tb.i0 && ci < tb.i0 + 64 && cj == j && ck >= tb.k0 && ck < tb.k1) ct.add_ra(ps, dra);
+    }
     // lambda*_p of the cell at state offset o
     auto lstar = [&](double lp, int o) { return o == centre ? lp - ps : lp; };
 
@@ -723,7 +732,13 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
 
         const int o = ocol + k * Z;
         const double lm[NF] = {cur.lp, cur.l[0], cur.l[1], cur.l[2], cur.l[3]};
-        GatherAcc a = gather_init(c, lm, o == centre, ps, cur.ub, cur.vb, cur.wb, cur.D);
+        const bool isc = o == centre;
+        // the centre's record holds lambda_p's terms; lambda*_p's differ by
+        // S times the unit p seed's
+        const double ub = isc ? cur.ub - ps * ct.cx[0] : cur.ub;
+        const double vb = isc ? cur.vb - ps * ct.cx[1] : cur.vb;
+        const double wb = isc ? cur.wb - ps * ct.cx[2] : cur.wb;
+        GatherAcc a = gather_init(c, lm, isc, ps, ub, vb, wb, cur.D);
         const double dt = cur.D.dt;
         const double au = cur.l[0] * dt, av = cur.l[1] * dt, aw = cur.l[2] * dt, at = cur.l[3] * dt;
         // the neighbour at (row, col) of the plane's buffer, with its x (or y)
@@ -800,11 +815,11 @@ __global__ __launch_bounds__(ADJ_THREADS) void nusselt_seed_kernel(Dims d, doubl
 
 // Partials of the record pass: one per block of any k-chunk tiling (the
 // chunking never yields more than nk/CAV_MIN_KC chunks per tile column),
-// plus one for the centre-cell launch, NF each.
+// NF each.
 long long record_partials(const Dims& d)
 {
     const long long tiles = (long long)((d.ni + SW_TI - 1) / SW_TI) * ((d.nj + SW_TJ - 1) / SW_TJ);
-    return (tiles * std::max(1, d.nk / CAV_MIN_KC) + 1) * NF;
+    return tiles * std::max(1, d.nk / CAV_MIN_KC) * NF;
 }
 
 }  // namespace
@@ -820,11 +835,11 @@ hipError_t launch_adjoint_step(const Dims& d, const Coef& c, const SweepGeom& g,
                                CStateT<double> q, CStateT<double> lam_in, StateT<double> lam_out, double* ws,
                                double* dthot, double* dra, hipStream_t s)
 {
-    double* psum = ws;                       // ws[0]: sum of lambda_p
+    double* cx = ws;                         // ws[0..3]: the centre's unit p seed terms
     double* part = ws + 8;
     const long long np = record_partials(d);
     double* rec = part + (np + 7) / 8 * 8;
-    if ((long long)(g.nblocks + 1) * NF > np) return hipErrorInvalidValue;
+    if ((long long)g.nblocks * NF > np) return hipErrorInvalidValue;
     hipError_t e;
 
     RaFactors rf;
@@ -834,27 +849,22 @@ hipError_t launch_adjoint_step(const Dims& d, const Coef& c, const SweepGeom& g,
     // the LDS tile gather reads the compact record, the one-cell gather the
     // full one
     const bool tile = gg.kc >= CAV_ADJ_TILE_MIN_KC;
-    // every record but the centre cell's; each block's sum of lambda_p
-    if (tile) record_kernel<true><<<g.nblocks, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, g, rf, q, lam_in, rec, part);
-    else record_kernel<false><<<g.nblocks, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, g, rf, q, lam_in, rec, part);
+    // every cell's record (the centre's seeded with lambda_p, plus its unit
+    // p seed terms in cx); each block's Ra term and sum of lambda_p
+    if (tile) record_kernel<true><<<g.nblocks, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, g, rf, q, lam_in, rec, part, cx);
+    else record_kernel<false><<<g.nblocks, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, g, rf, q, lam_in, rec, part, cx);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // the sum of lambda_p, the centre cell's record, the Ra cotangent
-    if (tile)
-        record_centre_kernel<true><<<1, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, rf, q, lam_in, psum, rec, part, g.nblocks,
-                                                                    dra);
-    else
-        record_centre_kernel<false><<<1, dim3(SW_TI, SW_TJ), 0, s>>>(d, c, rf, q, lam_in, psum, rec, part,
-                                                                     g.nblocks, dra);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the gather, with the rescale sum and the Ra cotangent's sum
+    const CentreTerms ct{part, g.nblocks, cx};
     if (tile) {
-        adjoint_gather_tile_kernel<ADJ_GTJ><<<gg.nblocks, dim3(64, ADJ_GTJ), 0, s>>>(d, c, gg, q, lam_in, psum, rec,
-                                                                                 lam_out, dthot);
+        adjoint_gather_tile_kernel<ADJ_GTJ><<<gg.nblocks, dim3(64, ADJ_GTJ), 0, s>>>(d, c, gg, q, lam_in, ct, rec,
+                                                                                 lam_out, dthot, dra);
     } else {
         // 8 j slabs (one per XCD), as many blocks for each as the widest needs
         const long long wmax = (d.nj + 7) / 8;
         const long long per_xcd = ((long long)d.ni * wmax * d.nk + ADJ_THREADS - 1) / ADJ_THREADS;
-        adjoint_gather_kernel<<<(unsigned)(8 * per_xcd), ADJ_THREADS, 0, s>>>(d, c, q, lam_in, psum, rec, lam_out,
-                                                                             dthot);
+        adjoint_gather_kernel<<<(unsigned)(8 * per_xcd), ADJ_THREADS, 0, s>>>(d, c, q, lam_in, ct, rec, lam_out,
+                                                                             dthot, dra);
     }
     return hipGetLastError();
 }

@@ -160,10 +160,9 @@ def test_adjoint_validation():
     g64, g32 = C.Grid(16, 12, 10), C.Grid(16, 12, 10, dtype=C.CAV_F32)
     need = C.cavity_adjoint_workspace_bytes(g64)
     # 8 head doubles + partials (rounded to 8: 5 per record-pass block, at
-    # most tiles * max(1, nk/2) blocks, and 5 for the centre-cell block)
-    # + an 8-value record per cell
+    # most tiles * max(1, nk/2) blocks) + an 8-value record per cell
     tiles = 1 * 2
-    nb = (tiles * max(1, 10 // 2) + 1) * 5
+    nb = tiles * max(1, 10 // 2) * 5
     assert need == 8 * (8 + -(-nb // 8) * 8 + 8 * 16 * 12 * 10)
     assert C.cavity_adjoint_workspace_bytes(g32) == 0
     G, P = ctypes.byref(g64.c()), ctypes.byref(C.Params().c())
