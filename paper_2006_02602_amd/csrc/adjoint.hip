@@ -166,21 +166,6 @@ __device__ __forceinline__ CellD cell_d(const CoefR<double>& c, double u, double
 
 __device__ __forceinline__ int centre_off(const Dims& d) { return cell_off(d, d.ni / 2, d.nj / 2, d.nk / 2); }
 
-// ---- fixed-order sum of per-block partials ----
-// Sum of part[b * stride] for b < n, by one whole wavefront: lane l adds
-// b = l, l + 64, ... in order, then a butterfly over the lanes.  IEEE
-// addition commutes, so every lane gets the same bits, and so does every
-// wavefront that calls it.  All 64 lanes must be active.
-__device__ double wave_sum(const double* __restrict__ part, int n, int stride)
-{
-    const int l = threadIdx.x & 63;
-    double acc = 0.0;
-    for (int b = l; b < n; b += 64) acc += part[(size_t)b * stride];
-#pragma unroll
-    for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 64);
-    return acc;
-}
-
 // ---- 2. record pass ----
 struct RaFactors {
     double nu, alpha, dtv;        // d(nu)/dRa, d(alpha)/dRa, d(dt_visc)/dRa
@@ -270,19 +255,32 @@ __global__ __launch_bounds__(SW_TI * SW_TJ) void record_kernel(Dims d, Coef cd, 
     sweep_tile<double, true, OwnAll, RecordEpiD<COMPACT>, 2>(d, c, tb, OwnAll{}, q, epi, partials, L);
 }
 
-// The rescale sum S (every record block's lambda_p partial) and, if dra is
-// not NULL, dra += the Ra partials of every record block minus S times the
-// unit p seed's Ra term at the centre (cx[3]): one whole wavefront, the one
-// holding the centre cell, so it happens once per reverse step.
+// The record pass's per-block partials (the Ra term, the sum of lambda_p)
+// and the centre's unit p seed terms cx.  sums() forms, in one whole
+// wavefront, the rescale sum S (every block's lambda_p partial) and the Ra
+// cotangent of the step: every block's Ra partial minus S times the unit
+// seed's Ra term, cx[3].  Lane l adds blocks l, l + 64, ... in order, then a
+// butterfly over the lanes: IEEE addition commutes, so every lane, and every
+// wavefront that calls it, gets the same bits.  All 64 lanes must be
+// active.
 struct CentreTerms {
     const double* part;
     int nblocks;
     const double* cx;
-    __device__ __forceinline__ double sum() const { return wave_sum(part + 1, nblocks, NF); }
-    __device__ __forceinline__ void add_ra(double S, double* dra) const
+    __device__ __forceinline__ void sums(double& S, double& ra) const
     {
-        const double v = wave_sum(part, nblocks, NF) - S * cx[3];
-        if ((threadIdx.x & 63) == 0) dra[0] += v;
+        double a = 0.0, b = 0.0;
+        for (int k = threadIdx.x & 63; k < nblocks; k += 64) {
+            b += part[(size_t)k * NF];
+            a += part[(size_t)k * NF + 1];
+        }
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) {
+            a += __shfl_xor(a, m, 64);
+            b += __shfl_xor(b, m, 64);
+        }
+        S = a;
+        ra = b - a * cx[3];
     }
 };
 
@@ -423,19 +421,27 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
     const long long r = cc / d.ni;
     const int j = j0 + (int)(r % w), k = (int)(r / w);
     const int ci = d.ni / 2, cj = d.nj / 2, ck = d.nk / 2;
-    // The rescale sum S, in every wavefront holding a cell within two of the
-    // centre (the cells that read the centre's seeds); the wavefront holding
-    // the centre adds the Ra term.  Every lane is still active here.
-    double S = 0.0;
-    if (__any(in && abs(i - ci) <= 2 && abs(j - cj) <= 2 && abs(k - ck) <= 2)) {
-        S = ct.sum();
-        if (dra && __any(in && i == ci && j == cj && k == ck)) ct.add_ra(S, dra);
-    }
-    if (!in) return;
     const long long idx = i + (long long)d.ni * (j + (long long)d.nj * k);
     const int o = cell_off(d, i, j, k);
     const int centre = centre_off(d);
     auto R = [&](int v, long long m) { return rec[(size_t)v * n + m]; };
+    double own[NREC_C];
+#pragma unroll
+    for (int v = 0; v < NREC_C; ++v) own[v] = R(v, idx);
+    double lm[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) lm[f] = lam.f[f][o];
+    // The rescale sum S, in every wavefront holding a cell within two of the
+    // centre (the cells that read the centre's seeds); the wavefront holding
+    // the centre adds the Ra term.  Every lane is still active here (lanes
+    // past the end loaded a real cell and return below).
+    double S = 0.0;
+    if (__any(in && abs(i - ci) <= 2 && abs(j - cj) <= 2 && abs(k - ck) <= 2)) {
+        double ra;
+        ct.sums(S, ra);
+        if (dra && __any(in && i == ci && j == cj && k == ck) && (threadIdx.x & 63) == 0) dra[0] += ra;
+    }
+    if (!in) return;
     // dt, X and Bp of the cell at state offset om, dense index m: its record,
     // or at the centre formed from lambda*_p (its record holds lambda_p's)
     auto dxb = [&](long long m, int om) {
@@ -443,12 +449,6 @@ __global__ __launch_bounds__(ADJ_THREADS) void adjoint_gather_kernel(Dims d, Coe
         return CellD{R(R_DT, m), {R(R_XX, m), R(R_XY, m), R(R_XZ, m)}, R(R_BP, m)};
     };
 
-    double own[NREC_C];
-#pragma unroll
-    for (int v = 0; v < NREC_C; ++v) own[v] = R(v, idx);
-    double lm[NF];
-#pragma unroll
-    for (int f = 0; f < NF; ++f) lm[f] = lam.f[f][o];
     const CellD od = dxb(idx, o);
     const bool isc = o == centre;
     if (isc) {
@@ -590,8 +590,9 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
     double ps = 0.0;
     if (ci >= tb.i0 - 2 && ci < tb.i0 + 66 && cj >= tb.j0 - 2 && cj < tb.j0 + TJ + 2 && ck >= tb.k0 - 2 &&
         ck < tb.k1 + 2) {
-        ps = ct.sum();
-        if (dra && ci >= tb.i0 && ci < tb.i0 + 64 && cj == j && ck >= tb.k0 && ck < tb.k1) ct.add_ra(ps, dra);
+        double ra;
+        ct.sums(ps, ra);
+        if (dra && ci >= tb.i0 && ci < tb.i0 + 64 && cj == j && ck >= tb.k0 && ck < tb.k1 && lane == 0) dra[0] += ra;
     }
     // lambda*_p of the cell at state offset o
     auto lstar = [&](double lp, int o) { return o == centre ? lp - ps : lp; };
