@@ -291,12 +291,15 @@ def test_reverse_step_dense_cotangent_matches_tangent(C, n, Ra):
 def test_reverse_step_full_size_tile_edges(C):
     """256^3 in the launch the reverse step is timed in: lam_out at cells on
     the edges of the gather's LDS tiles (i = 63, 64, 191, 192; j = 7, 8;
-    the k chunk edge 127, 128), at walls and corners, against central
+    the k chunk edge 127, 128), at walls and corners, and at the centre cell
+    (128, 128, 128: the corner of four tiles and the first plane of a k
+    chunk, where the rescale's transpose acts) and its neighbours, against central
     differences of the library's own forward step (cavity_step_from) along
     those cells: sum(lam * (step(q + h e) - step(q - h e))) / (2 h).  Away
-    from the cell's star the two steps agree bit for bit, so the sum holds
-    only the star's terms; h = 1e-6 keeps truncation (h^2) and rounding
-    (eps / h) near 1e-10 of the derivative."""
+    from the cell's star the two steps agree bit for bit (except the
+    rescale's shift of every p when the star holds the centre), so the sum
+    holds only the star's terms; h = 1e-6 keeps truncation (h^2) and
+    rounding (eps / h) near 1e-10 of the derivative."""
     import torch
     say("reverse step 256^3, tile edges vs central differences")
     g = C.Grid.cube(256)
@@ -312,7 +315,9 @@ def test_reverse_step_full_size_tile_edges(C):
     assert bool(torch.isfinite(ov[inner]).all())
     cells = [(0, 63, 7, 127), (1, 64, 8, 128), (2, 191, 7, 128), (3, 192, 8, 127), (4, 64, 7, 127),
              (0, 192, 255, 0), (1, 0, 8, 255), (4, 0, 0, 128), (2, 255, 7, 64), (3, 63, 0, 200),
-             (4, 255, 255, 255), (0, 1, 128, 1)]
+             (4, 255, 255, 255), (0, 1, 128, 1),
+             (0, 128, 128, 128), (1, 128, 128, 128), (0, 127, 128, 128), (0, 128, 126, 128),
+             (0, 128, 128, 127), (3, 130, 128, 128), (4, 128, 129, 128), (0, 128, 128, 130)]
     h = 1e-6
     qp, qm = torch.empty_like(q), torch.empty_like(q)
     a, b = torch.empty_like(q), torch.empty_like(q)
