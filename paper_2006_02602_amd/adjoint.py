@@ -6,7 +6,9 @@ cavity_adjoint_step) with step checkpointing.
 The forward run keeps the state every `every` steps (the checkpoints).  The
 reverse sweep walks the segments last to first: it recomputes the states of
 one segment from its checkpoint with cavity_step, then runs the reverse steps
-of that segment.  Memory: N/every checkpoints plus one segment of states;
+of that segment.  The recomputation of the next segment runs on a second
+stream while the reverse steps of the current one run, into the other of two
+segment buffers.  Memory: N/every checkpoints plus two segments of states;
 work: two forward runs plus N reverse steps.  Every step, forward or
 reverse, runs in the library's kernels; this module only orders the calls
 and holds torch buffers.
@@ -61,13 +63,14 @@ class NusseltAdjoint:
         self._b = dict(
             dev=device,
             ckpt=torch.zeros((max(len(self.segs), 1), n), **f64),
-            states=torch.zeros((max(self.every - 1, 1), n), **f64),
+            states=torch.zeros((2, max(self.every - 1, 1), n), **f64),
             q=torch.zeros(n, **f64), tmp=torch.zeros(n, **f64),
             ws=torch.zeros(cavity_workspace_bytes(g) // 8, **f64),
             lam=(torch.zeros(n, **f64), torch.zeros(n, **f64)),
             dth=torch.zeros(g.nj * g.nk, **f64), dra=torch.zeros(1, **f64),
             aws=torch.zeros(cavity_adjoint_workspace_bytes(g) // 8, **f64),
-            theta=torch.zeros(g.nj * g.nk, **f64))
+            theta=torch.zeros(g.nj * g.nk, **f64),
+            side=torch.cuda.Stream(device=device))
         self._g = None
         return self._b
 
@@ -85,29 +88,63 @@ class NusseltAdjoint:
         self.J = cavity_nusselt(self.grid, self.prm, q, B["ws"])
         return self.J
 
+    def _recompute(self, s: int, b: int):
+        """The states of segment s, recomputed from its checkpoint into
+        segment buffer b on the current stream (its first state is the
+        checkpoint itself)."""
+        B, g, prm = self._b, self.grid, self.prm
+        states = [B["ckpt"][s]]
+        for m in range(1, self.segs[s][1]):
+            st = B["states"][b][m - 1]
+            cavity_step_from(g, prm, states[-1], st)
+            states.append(st)
+        return states
+
     def _reverse(self):
-        """Every launch of the backward pass, on the current stream: seed
-        the cotangent of J, then per segment (last to first) recompute its
-        states from the checkpoint and run its reverse steps.  The cotangent
-        alternates between two buffers (a reverse step reads its input at
-        every cell's neighbours, so it cannot write in place); after N steps
-        it is in buffer N mod 2."""
+        """Every launch of the backward pass, issued from the current stream:
+        seed the cotangent of J, then per segment (last to first) run its
+        reverse steps over its recomputed states.  The states of the next
+        segment are recomputed on a second stream meanwhile, into the other
+        segment buffer (once the reverse steps that read that buffer before
+        are done); the current stream waits for them before using them and
+        joins the second stream at the end.  The cotangent alternates between
+        two buffers (a reverse step reads its input at every cell's
+        neighbours, so it cannot write in place); after N steps it is in
+        buffer N mod 2."""
+        import torch
         B, g, prm = self._b, self.grid, self.prm
         lam, dth, dra = B["lam"], B["dth"], B["dra"]
+        main, side = torch.cuda.current_stream(), B["side"]
         dth.zero_()
         dra.zero_()
         cur = 0
         cavity_nusselt_adjoint(g, prm, lam[cur], dth)
-        for s in reversed(range(len(self.segs))):
-            length = self.segs[s][1]
-            states = [B["ckpt"][s]]
-            for m in range(1, length):
-                st = B["states"][m - 1]
-                cavity_step_from(g, prm, states[-1], st)
-                states.append(st)
+        order = list(reversed(range(len(self.segs))))
+        if not order:
+            return
+        states = self._recompute(order[0], 0)
+        side.wait_stream(main)
+        free = [None, None]              # main has finished reading buffer b
+        done = [None, None]              # side has finished writing buffer b
+        nxt = None
+        for idx, s in enumerate(order):
+            b = idx % 2
+            if idx + 1 < len(order):
+                with torch.cuda.stream(side):
+                    if free[1 - b] is not None:
+                        side.wait_event(free[1 - b])
+                    nxt = self._recompute(order[idx + 1], 1 - b)
+                    done[1 - b] = torch.cuda.Event()
+                    done[1 - b].record(side)
+            if idx > 0:
+                main.wait_event(done[b])
             for st in reversed(states):
                 cavity_adjoint_step(g, prm, st, lam[cur], lam[1 - cur], B["aws"], dth, dra)
                 cur = 1 - cur
+            free[b] = torch.cuda.Event()
+            free[b].record(main)
+            states = nxt
+        main.wait_stream(side)
 
     def backward(self):
         """(dJ/dtheta (nj*nk), dJ/dRa (1), dJ/dq0 (flat state, zero ghosts))."""
