@@ -7,21 +7,30 @@
 // pressure rescale p^{n+1} = p* - p*(centre).  Given the cotangent lambda of
 // q^{n+1}, the reverse step returns the cotangent of q^n and adds the
 // cotangents of Theta and of Ra:
-//   1. lambda*_p(centre) = lambda_p(centre) - sum over cells of lambda_p
-//      (transpose of the rescale); lambda* = lambda elsewhere;
+//   1. the transpose of the rescale: lambda*_p(centre) = lambda_p(centre) -
+//      S, S the sum over cells of lambda_p; lambda* = lambda elsewhere;
 //   2. record pass, per cell m (the forward sweep's k-marching tile, so the
-//      stars come from LDS and registers): seeds a_f = lambda*_f dt for R_f
-//      and b = sum_f lambda*_f R_f for dt, then the hand-written reverse of
+//      stars come from LDS and registers): seeds a_f = lambda_f dt for R_f
+//      and b = sum_f lambda_f R_f for dt, then the hand-written reverse of
 //      the residual.  The cotangents of m's 41 star values are linear in a
-//      few per-cell numbers -- a_u, a_v, a_w, a_T, eps4 a_p lambda_i/h_i
-//      (three), beta^2 a_p and the centre terms of u, v, w -- which are
-//      stored (11 doubles per cell); nu, alpha and the viscous step limit get
-//      their cotangents reduced per block into the Ra cotangent;
+//      few per-cell numbers -- a_u .. a_T (lambda_f dt), eps4 a_p
+//      lambda_i/h_i (three), beta^2 a_p, dt and the centre terms of u, v, w.
+//      Only the last three depend on m's star; the rest follow from m's
+//      velocity and lambda.  The pass stores 8 (dt, the three dissipation
+//      terms, Bp and the centre terms) or, for the LDS tile gather, only
+//      the 3 centre terms; nu, alpha and the viscous step limit get their
+//      cotangents reduced per block into partials of the Ra cotangent, and
+//      each block sums its lambda_p.  Everything is linear in the seeds, so
+//      the centre cell is seeded with lambda_p like the others and also
+//      stores its centre terms and Ra term for a unit p seed;
 //   3. gather pass, per cell e: lambda*(e) plus every star cotangent that
 //      lands on e, rebuilt from the records of the cells whose stars reach e
-//      (13 for p, 7 for u v w T) and their velocities; cells within two of a
-//      wall add the transposed wall rules of the ghosts their neighbours read
-//      (and the x = 0 wall rows add to dJ/dTheta).
+//      (13 for p, 7 for u v w T), their velocities and lambda; cells within
+//      two of a wall add the transposed wall rules of the ghosts their
+//      neighbours read (and the x = 0 wall rows add to dJ/dTheta).  The
+//      cells that read the centre form S from the record blocks' partials
+//      and take the centre's values for lambda*_p (the unit seed's terms
+//      times S subtracted); the one holding the centre adds the Ra sum.
 // Every sum runs in a fixed order, so results are run-to-run identical.
 #include "cavity_internal.h"
 #include "stencil.h"
