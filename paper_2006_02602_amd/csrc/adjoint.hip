@@ -653,18 +653,30 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
             H.v[3] = lam.f[FP][o];
         }
     };
+    // a velocity + lambda_p slot's values, formed in place (one plane
+    // before they are stored): the dissipation term across the halo, dt,
+    // Bp and the velocity component across it
+    auto form_halo = [&](int k, Halo& H) {
+        if (hkind == 0 || hkind == 1) {
+            const CellD D = cell_d(c, H.v[0], H.v[1], H.v[2], lstar(H.v[3], hoff + k * Z));
+            const double V = hrow ? H.v[1] : H.v[0];
+            H.v[0] = hrow ? D.X[1] : D.X[0];
+            H.v[1] = D.dt;
+            H.v[2] = D.Bp;
+            H.v[3] = V;
+        }
+    };
     // what the slot puts into the plane's buffer B
-    auto store_halo = [&](int k, const Halo& H, double* B) {
+    auto store_halo = [&](const Halo& H, double* B) {
         if (hkind == 2) {
 #pragma unroll
             for (int f = 0; f < 4; ++f) B[hpos + (L_LU + f) * T::VS] = H.v[f];
         } else if (hkind >= 0) {
-            const CellD D = cell_d(c, H.v[0], H.v[1], H.v[2], lstar(H.v[3], hoff + k * Z));
-            B[hpos + (hrow ? L_XY : L_XX) * T::VS] = hrow ? D.X[1] : D.X[0];
+            B[hpos + (hrow ? L_XY : L_XX) * T::VS] = H.v[0];
             if (hkind == 0) {
-                B[hpos + L_DT * T::VS] = D.dt;
-                B[hpos + L_BP * T::VS] = D.Bp;
-                B[hpos + (hrow ? L_V : L_U) * T::VS] = hrow ? H.v[1] : H.v[0];
+                B[hpos + L_DT * T::VS] = H.v[1];
+                B[hpos + L_BP * T::VS] = H.v[2];
+                B[hpos + (hrow ? L_V : L_U) * T::VS] = H.v[3];
             }
         }
     };
@@ -724,11 +736,13 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
     if (k0 + 2 < k1) load_halo(k0 + 2, H2);
     derive(k0, C0);
     if (k0 + 1 < nk) derive(k0 + 1, C1);
+    form_halo(k0, H0);
 
     // plane k: cur = plane k, nxt = k+1, nn2 = k+2 (its dt, X and Bp are
-    // formed here; only its z dissipation term is read); cur and H are
-    // reloaded with plane k+3 once used
-    auto body = [&](int k, Column& cur, Column& nxt, Column& nn2, Halo& H) __attribute__((always_inline)) {
+    // formed here; only its z dissipation term is read); H = plane k's
+    // halo, Hn = plane k+1's (formed here); cur and H are reloaded with
+    // plane k+3 once used
+    auto body = [&](int k, Column& cur, Column& nxt, Column& nn2, Halo& H, Halo& Hn) __attribute__((always_inline)) {
         double* B = L + ((k - k0) & 1) * T::BUF;
         {
             const double own[NLV] = {cur.l[0], cur.l[1], cur.l[2], cur.l[3], cur.D.dt,
@@ -736,7 +750,7 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
 #pragma unroll
             for (int v = 0; v < NLV; ++v) B[T::at(v, row, lane)] = own[v];
         }
-        store_halo(k, H, B);
+        store_halo(H, B);
         if (k + 3 < k1) load_halo(k + 3, H);
         __syncthreads();
 
@@ -789,6 +803,7 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
                         nullptr);
         }
         if (active) gather_store<true>(a, out, o);
+        if (k + 1 < k1) form_halo(k + 1, Hn);
 
         xm2 = prv.X;
         prv = Nb{au, av, aw, at, cur.D.X[2], cur.D.Bp, cur.w * Hz};
@@ -798,9 +813,9 @@ __global__ __launch_bounds__(64 * TJ) void adjoint_gather_tile_kernel(Dims d, Co
         if (k + 3 < nk && k + 1 < k1) load(k + 3, cur);
     };
     for (int k = k0; k < k1; k += 3) {
-        body(k, C0, C1, C2, H0);
-        if (k + 1 < k1) body(k + 1, C1, C2, C0, H1);
-        if (k + 2 < k1) body(k + 2, C2, C0, C1, H2);
+        body(k, C0, C1, C2, H0, H1);
+        if (k + 1 < k1) body(k + 1, C1, C2, C0, H1, H2);
+        if (k + 2 < k1) body(k + 2, C2, C0, C1, H2, H0);
     }
 }
 
